@@ -1,0 +1,159 @@
+/*
+ * p3m.h -- C ABI of libp3m.so, the MI355X (gfx950) P3M periodic-gravity force.
+ *
+ * The library computes the gravitational force of the P3M method of the
+ * CONCEPT N-body code (CONCEPT User's Guide, arXiv:1510.07621): a
+ * particle-mesh long-range part and a short-range pair sum, split at a scale
+ * r_s and cut off at r_c, in a periodic cubic comoving box, for one particle
+ * group with Plummer softening; plus the kick and drift particle updates.
+ * Guide references: Ch. 1 (PP, PM and P3M gravity); Ch. 5 "Parameters"
+ * (boxsize, PM_gridsize, PM_scale, P3M_cutoff, softeningfactors,
+ * kick_algorithms); Ch. 6 (particle data: one mass per group, comoving
+ * positions posx/posy/posz and momenta momx/momy/momz in
+ * length*mass/time); Ch. 8 (drift and kick tests).
+ *
+ * Mathematics (the guide names the method but gives no formulas; these are
+ * the definitions this library implements):
+ *   h = box / grid_n, r_s = rs_cells * h, r_c = cutoff_rs * r_s.
+ *   PP:  a_i = -G sum_{j != i, r < r_c} m_j r_ij f(r) / (r^2 + eps^2)^(3/2),
+ *        r_ij the minimum-image separation, r = |r_ij|,
+ *        f(r) = erfc(r/(2 r_s)) + r/(r_s sqrt(pi)) exp(-r^2/(4 r_s^2)).
+ *   PM:  cloud-in-cell deposit to nodes c*h; FFT; multiply by
+ *        G(k) = -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^deconv_power), G(0) = 0,
+ *        W(k) = prod_d sinc^2(pi n_d / grid_n); inverse FFT; central
+ *        difference gradient (fd_order 4 or 2); CIC interpolation; a = -grad.
+ *   F_i = m_i (a_PP + a_PM).
+ *
+ * Conventions for every call:
+ *   - Device arrays are plain HIP device pointers on the current device.
+ *     Vector arrays are structure-of-arrays: x[0..n), then y, then z.
+ *   - pos components must lie in [0, box). Positions outside are clamped to
+ *     the nearest cell for binning (memory-safe) but give undefined forces.
+ *   - Work is enqueued on a HIP stream and the call returns without
+ *     synchronising. Asynchronous device errors surface at the caller's
+ *     next synchronisation. Outputs are overwritten, never accumulated.
+ *   - Argument errors are detected before any work is enqueued; nothing is
+ *     written then. The library never aborts and never throws across the ABI.
+ *   - The caller owns all particle arrays; a plan owns its workspace,
+ *     allocated once by p3m_plan_create. Force calls allocate nothing.
+ *   - A plan is not thread-safe: use one plan from one host thread and one
+ *     stream at a time.
+ */
+#ifndef P3M_H
+#define P3M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define P3M_OK       0
+#define P3M_EINVAL  -1  /* null pointer, n < 0, n > n_max, bad parameter     */
+#define P3M_ENOMEM  -2  /* device allocation failed in p3m_plan_create        */
+#define P3M_EHIP    -3  /* a HIP runtime call or kernel launch failed          */
+#define P3M_ERANGE  -4  /* r_c >= box/2 (minimum image insufficient)           */
+
+/* Arithmetic of the force path (particle storage, kick and drift stay FP64). */
+#define P3M_FP64     0  /* pair loop, FFT and grids in double precision        */
+#define P3M_FP32     1  /* pair loop, FFT and grids in single precision, pair
+                           separations from cell-relative FP32 offsets        */
+
+typedef struct p3m_params {
+  int32_t grid_n;       /* PM_gridsize: power of two, 16..512                        */
+  int32_t precision;    /* P3M_FP64 or P3M_FP32                                      */
+  int32_t fd_order;     /* 4 (default) or 2: central-difference gradient order       */
+  int32_t deconv_power; /* 2 (default) or 0: powers of the CIC window divided out    */
+  double  box;          /* boxsize L > 0 (comoving side of the periodic cube)        */
+  double  rs_cells;     /* PM_scale: r_s in PM cells, > 0 (1.25 typical)             */
+  double  cutoff_rs;    /* P3M_cutoff: r_c in units of r_s, > 0 (4.5 typical)        */
+  double  softening;    /* Plummer radius eps as a length, >= 0                      */
+  double  G;            /* gravitational constant                                    */
+} p3m_params;
+
+/* Opaque plan: derived geometry, device workspace, and optional stage timers. */
+typedef struct p3m_plan p3m_plan;
+
+/* Fill *out with the documented defaults for a grid of grid_n^3 cells in a
+ * box of side box: FP32, fd_order 4, deconv_power 2, rs_cells 1.25,
+ * cutoff_rs 4.5, softening 0, G 1. Returns P3M_EINVAL for a null out. */
+int p3m_params_default(p3m_params* out, int32_t grid_n, double box);
+
+/* Create a plan for up to n_max particles whose work runs on hip_stream
+ * (a hipStream_t; NULL = the null stream). Validates the parameters
+ * (EINVAL for a non-power-of-two or out-of-range grid, box <= 0,
+ * rs_cells <= 0, cutoff_rs <= 0, softening < 0, n_max < 0 or
+ * n_max >= 2^31; ERANGE when r_c >= box/2), then allocates the workspace
+ * (ENOMEM on failure; nothing is leaked). *out is set only on success. */
+int p3m_plan_create(const p3m_params* params, int64_t n_max, void* hip_stream,
+                    p3m_plan** out);
+
+/* Release the plan and its workspace. Synchronises the plan's stream first.
+ * A null plan is a no-op returning P3M_OK. */
+int p3m_plan_destroy(p3m_plan* plan);
+
+/* Change the stream later calls on this plan enqueue on. */
+int p3m_plan_set_stream(p3m_plan* plan, void* hip_stream);
+
+/* Full P3M force (PP + PM) on n particles.
+ *   pos         device, double [3][n], components in [0, box)
+ *   mass        device, double [n], or NULL to give every particle mass_scalar
+ *               (one mass per particle group, guide Ch. 6)
+ *   force       device output [3][n]: double if force_fp32 == 0, float otherwise;
+ *               must not overlap pos or mass
+ * n == 0 is a successful no-op. */
+int p3m_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+              double mass_scalar, void* force, int32_t force_fp32);
+
+/* Long-range (PM) part only: F_i = m_i a_PM(x_i). Same arguments. */
+int pm_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+             double mass_scalar, void* force, int32_t force_fp32);
+
+/* Short-range (PP) part only: F_i = m_i a_PP(x_i). Same arguments. */
+int pp_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+             double mass_scalar, void* force, int32_t force_fp32);
+
+/* Count the ordered pairs (i, j != i) with minimum-image separation in
+ * (0, r_c), the pairs the short-range sum evaluates (a diagnostic for
+ * interaction rates). count_out: device int64 [1], overwritten. Separations
+ * are tested in the plan's precision. */
+int p3m_pair_count(p3m_plan* plan, int64_t n, const double* pos,
+                   int64_t* count_out);
+
+/* Kick (guide Ch. 5 kick_algorithms, Ch. 8 kick tests): p <- p + c_kick * F,
+ * each product and sum one IEEE double operation (no fused multiply-add).
+ * mom: device double [3][n] in place; force: device [3][n], float if
+ * force_fp32 != 0 else double. */
+int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32,
+             double c_kick, void* hip_stream);
+
+/* Drift (guide Ch. 8 drift test: comoving motion, crossing box faces):
+ * x <- wrap(x + c_drift * (p / m)), wrap(y) = y - box*floor(y/box) and a
+ * result equal to box becomes 0; one IEEE double operation per step, no
+ * fused multiply-add. pos: device double [3][n] in place; mom: device double
+ * [3][n]; mass: device double [n] or NULL for mass_scalar. box > 0. */
+int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
+              double mass_scalar, double c_drift, double box, void* hip_stream);
+
+/* Stage timers. When enabled, each force call records HIP events around its
+ * stages on the plan's stream; p3m_stage_times then synchronises the stream
+ * and writes the last call's stage durations in milliseconds (0 for stages
+ * that did not run) to ms_out[0..n_stages). Stage indices: */
+#define P3M_STAGE_BIN      0  /* cell keys, counts, scan, scatter and pack   */
+#define P3M_STAGE_DEPOSIT  1  /* CIC mass deposit                              */
+#define P3M_STAGE_FFT      2  /* forward FFT, Green's function, inverse FFT   */
+#define P3M_STAGE_INTERP   3  /* finite-difference gradient + interpolation   */
+#define P3M_STAGE_PP       4  /* short-range pair loop (+ combine, unpermute) */
+#define P3M_NUM_STAGES     5
+int p3m_set_timing(p3m_plan* plan, int32_t enable);
+int p3m_stage_times(p3m_plan* plan, double* ms_out, int32_t n_stages);
+
+/* Static text for a status code ("unknown status" for others). */
+const char* p3m_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P3M_H */

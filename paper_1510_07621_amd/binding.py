@@ -1,0 +1,246 @@
+"""Python binding of libp3m.so: the same entry points, argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor shapes,
+dtypes and devices, passes raw device pointers and the current PyTorch (HIP)
+stream, and turns status codes into exceptions. PyTorch supplies device
+memory and streams. Importing this module loads the library and raises
+``RuntimeError`` if it has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libp3m.so")
+
+P3M_OK, P3M_EINVAL, P3M_ENOMEM, P3M_EHIP, P3M_ERANGE = 0, -1, -2, -3, -4
+P3M_FP64, P3M_FP32 = 0, 1
+STAGES = ("bin", "deposit", "fft", "interp", "pp")
+
+
+class P3MParams(ctypes.Structure):
+    _fields_ = [
+        ("grid_n", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("fd_order", ctypes.c_int32),
+        ("deconv_power", ctypes.c_int32),
+        ("box", ctypes.c_double),
+        ("rs_cells", ctypes.c_double),
+        ("cutoff_rs", ctypes.c_double),
+        ("softening", ctypes.c_double),
+        ("G", ctypes.c_double),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run `python -m paper_1510_07621_amd.build` "
+            "(the force path has no fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "p3m_params_default": (ctypes.c_int, [ctypes.POINTER(P3MParams), i32, dbl]),
+        "p3m_plan_create": (ctypes.c_int, [ctypes.POINTER(P3MParams), i64, vp,
+                                           ctypes.POINTER(vp)]),
+        "p3m_plan_destroy": (ctypes.c_int, [vp]),
+        "p3m_plan_set_stream": (ctypes.c_int, [vp, vp]),
+        "p3m_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
+        "pm_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
+        "pp_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
+        "p3m_pair_count": (ctypes.c_int, [vp, i64, vp, vp]),
+        "p3m_kick": (ctypes.c_int, [i64, vp, vp, i32, dbl, vp]),
+        "p3m_drift": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, dbl, vp]),
+        "p3m_set_timing": (ctypes.c_int, [vp, i32]),
+        "p3m_stage_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), i32]),
+        "p3m_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "p3m_stencil_rows": (i32, [i32, dbl, ctypes.POINTER(i32), i32]),
+        "p3m_group_edge": (i32, [i64, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def strerror(status: int) -> str:
+    return _lib.p3m_strerror(status).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status == P3M_OK:
+        return
+    msg = f"{what}: {strerror(status)} (status {status})"
+    if status in (P3M_EINVAL, P3M_ERANGE):
+        raise ValueError(msg)
+    raise RuntimeError(msg)
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _vec3(t: torch.Tensor, name: str, dtype=torch.float64) -> int:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype or t.dim() != 2 or t.shape[0] != 3 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous (3, n) {dtype} tensor")
+    return int(t.shape[1])
+
+
+def _mass(mass, n):
+    if mass is None or isinstance(mass, (int, float)):
+        return None, float(1.0 if mass is None else mass)
+    if (not isinstance(mass, torch.Tensor) or mass.device.type != "cuda" or
+            mass.dtype != torch.float64 or mass.shape != (n,) or not mass.is_contiguous()):
+        raise ValueError("mass must be a scalar or a contiguous (n,) float64 GPU tensor")
+    return mass, 0.0
+
+
+def stencil_rows(g: int, radius_cells: float):
+    """Neighbour stencil rows (dx, dy, dz_lo, dz_hi) of a g^3-cell i-group."""
+    n = _lib.p3m_stencil_rows(g, radius_cells, None, 0)
+    _check(min(n, 0), "p3m_stencil_rows")
+    buf = (ctypes.c_int32 * (4 * n))()
+    _lib.p3m_stencil_rows(g, radius_cells, buf, n)
+    return [tuple(buf[4 * k:4 * k + 4]) for k in range(n)]
+
+
+def group_edge(n: int, grid_n: int) -> int:
+    return int(_lib.p3m_group_edge(n, grid_n))
+
+
+@dataclass
+class Params:
+    """Plan parameters (guide Ch. 5: PM_gridsize, boxsize, PM_scale,
+    P3M_cutoff, softeningfactors; the softening here is an absolute length)."""
+    grid_n: int
+    box: float = 1.0
+    rs_cells: float = 1.25
+    cutoff_rs: float = 4.5
+    softening: float = 0.0
+    G: float = 1.0
+    precision: str = "fp32"      # "fp32" or "fp64"
+    fd_order: int = 4
+    deconv_power: int = 2
+
+    def to_c(self) -> P3MParams:
+        if self.precision not in ("fp32", "fp64"):
+            raise ValueError("precision must be 'fp32' or 'fp64'")
+        return P3MParams(int(self.grid_n),
+                         P3M_FP32 if self.precision == "fp32" else P3M_FP64,
+                         int(self.fd_order), int(self.deconv_power), float(self.box),
+                         float(self.rs_cells), float(self.cutoff_rs),
+                         float(self.softening), float(self.G))
+
+
+class Plan:
+    """Owns a libp3m plan (workspace for up to ``n_max`` particles)."""
+
+    def __init__(self, params: Params, n_max: int, stream=None):
+        self.params = params
+        self.n_max = int(n_max)
+        c = params.to_c()
+        h = ctypes.c_void_p()
+        _check(_lib.p3m_plan_create(ctypes.byref(c), self.n_max, _stream_ptr(stream),
+                                    ctypes.byref(h)), "p3m_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_lib.p3m_plan_destroy(self._h), "p3m_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _handle(self):
+        if self._h is None:
+            raise ValueError("plan is closed")
+        _check(_lib.p3m_plan_set_stream(self._h, _stream_ptr()), "p3m_plan_set_stream")
+        return self._h
+
+    def _force(self, fn, name, pos, mass, out, fp32_out):
+        n = _vec3(pos, "pos")
+        m, ms = _mass(mass, n)
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float32 if fp32_out else torch.float64,
+                              device=pos.device)
+        else:
+            fp32_out = out.dtype == torch.float32
+            if _vec3(out, "out", out.dtype) != n or out.dtype not in (torch.float32,
+                                                                      torch.float64):
+                raise ValueError("out must be (3, n) float32 or float64")
+        _check(fn(self._handle(), n, _ptr(pos), _ptr(m), ms, _ptr(out),
+                  1 if fp32_out else 0), name)
+        return out
+
+    def force(self, pos, mass=None, out=None, fp32_out=False):
+        """Full P3M force F = m (a_PP + a_PM), shape (3, n)."""
+        return self._force(_lib.p3m_force, "p3m_force", pos, mass, out, fp32_out)
+
+    def pm_force(self, pos, mass=None, out=None, fp32_out=False):
+        return self._force(_lib.pm_force, "pm_force", pos, mass, out, fp32_out)
+
+    def pp_force(self, pos, mass=None, out=None, fp32_out=False):
+        return self._force(_lib.pp_force, "pp_force", pos, mass, out, fp32_out)
+
+    def pair_count(self, pos) -> int:
+        """Ordered pairs with 0 < r < r_c (synchronises to return the count)."""
+        n = _vec3(pos, "pos")
+        cnt = torch.zeros(1, dtype=torch.int64, device=pos.device)
+        _check(_lib.p3m_pair_count(self._handle(), n, _ptr(pos), _ptr(cnt)),
+               "p3m_pair_count")
+        return int(cnt.item())
+
+    def set_timing(self, enable: bool = True):
+        _check(_lib.p3m_set_timing(self._handle(), 1 if enable else 0), "p3m_set_timing")
+
+    def stage_times(self) -> dict:
+        buf = (ctypes.c_double * len(STAGES))()
+        _check(_lib.p3m_stage_times(self._h, buf, len(STAGES)), "p3m_stage_times")
+        return {k: float(v) for k, v in zip(STAGES, buf)}
+
+
+def kick(mom: torch.Tensor, force: torch.Tensor, c_kick: float) -> torch.Tensor:
+    """p <- p + c_kick F in place (FP64 momenta; F float32 or float64)."""
+    n = _vec3(mom, "mom")
+    if _vec3(force, "force", force.dtype) != n or force.dtype not in (torch.float32,
+                                                                       torch.float64):
+        raise ValueError("force must be (3, n) float32 or float64")
+    _check(_lib.p3m_kick(n, _ptr(mom), _ptr(force), 1 if force.dtype == torch.float32 else 0,
+                         float(c_kick), _stream_ptr()), "p3m_kick")
+    return mom
+
+
+def drift(pos: torch.Tensor, mom: torch.Tensor, mass, c_drift: float, box: float):
+    """x <- wrap(x + c_drift p / m) in place."""
+    n = _vec3(pos, "pos")
+    if _vec3(mom, "mom") != n:
+        raise ValueError("mom must match pos")
+    m, ms = _mass(mass, n)
+    _check(_lib.p3m_drift(n, _ptr(pos), _ptr(mom), _ptr(m), ms, float(c_drift), float(box),
+                          _stream_ptr()), "p3m_drift")
+    return pos

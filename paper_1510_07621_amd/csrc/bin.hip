@@ -1,0 +1,237 @@
+// Counting-sort binning of particles into the cells of the PM grid, and the
+// work list of the pair loop.
+//
+// Cells are the grid's own cells (side h = box / grid_n), indexed
+// c = (cx * ng + cy) * ng + cz (z fastest), so each (cx, cy) column of cells is
+// one contiguous run of particles after sorting. Steps:
+//   1. keys + histogram: cell of each particle; atomic count per cell, whose
+//      return value is the particle's rank inside the cell;
+//   2. exclusive scan of the counts -> first slot of every cell;
+//   3. scatter + pack: each particle goes to slot start[c] + rank as a record
+//      of its offset from the cell's lower corner (in the path's precision)
+//      and its mass, with its input index (perm) and cell (skey).
+// The order inside a cell follows the atomic ranks, so it can differ between
+// runs; every later step is a sum, so only rounding depends on it.
+#include "p3m_internal.h"
+
+namespace p3m {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kScanItems = 8;                       // per thread
+constexpr int kScanTile = kThreads * kScanItems;    // per block
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// Cell coordinate of t = x / h, clamped into [0, ng) (NaN -> 0).
+__device__ __forceinline__ int cell_coord(double t, int ng) {
+  t = fmax(floor(t), 0.0);
+  t = fmin(t, (double)(ng - 1));
+  return (int)t;
+}
+
+__global__ void k_bin_count(int64_t n, const double* __restrict__ pos, int ng, int lg,
+                            double inv_h, int32_t* __restrict__ key,
+                            int32_t* __restrict__ rank, int32_t* __restrict__ count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int cx = cell_coord(pos[i] * inv_h, ng);
+  int cy = cell_coord(pos[n + i] * inv_h, ng);
+  int cz = cell_coord(pos[2 * n + i] * inv_h, ng);
+  int c = (((cx << lg) | cy) << lg) | cz;
+  key[i] = c;
+  rank[i] = atomicAdd(&count[c], 1);
+}
+
+template <typename T>
+__global__ void k_scatter(int64_t n, const double* __restrict__ pos,
+                          const double* __restrict__ mass, double mass_scalar, int ng,
+                          int lg, double h, const int32_t* __restrict__ key,
+                          const int32_t* __restrict__ rank,
+                          const int32_t* __restrict__ start, int32_t* __restrict__ perm,
+                          int32_t* __restrict__ skey, typename Vec<T>::v4* __restrict__ rec) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = key[i];
+  int dst = start[c] + rank[i];
+  int mask = ng - 1;
+  int cz = c & mask, cy = (c >> lg) & mask, cx = c >> (2 * lg);
+  typename Vec<T>::v4 r;
+  r.x = (T)(pos[i] - cx * h);
+  r.y = (T)(pos[n + i] - cy * h);
+  r.z = (T)(pos[2 * n + i] - cz * h);
+  r.w = (T)(mass ? mass[i] : mass_scalar);
+  rec[dst] = r;
+  perm[dst] = (int32_t)i;
+  skey[dst] = c;
+}
+
+// ---- exclusive scan of int32 (three kernels: tiles, tile sums, add) ----
+
+__device__ __forceinline__ int wave_inclusive(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over the block; returns the block total.
+__device__ __forceinline__ int block_exclusive(int v, int* __restrict__ wsum, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = wave_inclusive(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    int s = wsum[k];
+    if (k < w) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - v;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_tiles(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t len,
+             int32_t* __restrict__ tile_sum) {
+  __shared__ int wsum[kThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int local = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < len) ? in[base + k] : 0;
+    local += v[k];
+  }
+  int total;
+  int run = block_exclusive(local, wsum, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < len) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the tile sums in place; writes the grand
+// total to *grand.
+__global__ void __launch_bounds__(1024)
+k_scan_sums(int32_t* __restrict__ sums, int nt, int32_t* __restrict__ grand) {
+  __shared__ int wsum[1024 / 64];
+  int carry = 0;
+  for (int b = 0; b < nt; b += blockDim.x) {
+    int i = b + threadIdx.x;
+    int v = i < nt ? sums[i] : 0;
+    int total;
+    int ex = block_exclusive(v, wsum, total);
+    if (i < nt) sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_add(int32_t* __restrict__ out, int64_t len, const int32_t* __restrict__ tile_off) {
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int add = tile_off[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanTile; k += kThreads) {
+    int64_t i = base + k;
+    if (i < len) out[i] += add;
+  }
+}
+
+// ---- pair-loop work list ----
+
+__global__ void k_group_chunks(const int32_t* __restrict__ start, int ng, int lg, int G,
+                               int lgG, int64_t ngroup, int32_t* __restrict__ gchunk) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroup) return;
+  const int lgd = lg - lgG, md = (1 << lgd) - 1;
+  int gz = (int)(g & md), gy = (int)((g >> lgd) & md), gx = (int)(g >> (2 * lgd));
+  int cnt = 0;
+  for (int a = 0; a < G; ++a)
+    for (int b = 0; b < G; ++b) {
+      int c0 = ((((gx * G + a) << lg) | (gy * G + b)) << lg) | (gz * G);
+      cnt += start[c0 + G] - start[c0];
+    }
+  gchunk[g] = (cnt + 63) >> 6;
+}
+
+__global__ void k_emit_items(const int32_t* __restrict__ gchunk,
+                             const int32_t* __restrict__ goff, int64_t ngroup,
+                             int2* __restrict__ items) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroup) return;
+  int nc = gchunk[g], o = goff[g];
+  for (int c = 0; c < nc; ++c) items[o + c] = make_int2((int)g, c);
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int scan_tmp_size(int64_t len) { return (int)((len + kScanTile - 1) / kScanTile) + 1; }
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t b = (n + kThreads - 1) / kThreads;
+  unsigned blocks = (unsigned)(b < 65536 ? b : 65536);
+  k_fill_i32<<<blocks, kThreads, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+// out[0..len) = exclusive scan of in[0..len); out[len] = total. tmp needs
+// scan_tmp_size(len) entries.
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp,
+                       hipStream_t s) {
+  int nt = (int)((len + kScanTile - 1) / kScanTile);
+  if (nt == 0) return launch_fill_i32(out, 1, 0, s);
+  k_scan_tiles<<<nt, kThreads, 0, s>>>(in, out, len, tmp);
+  k_scan_sums<<<1, 1024, 0, s>>>(tmp, nt, out + len);
+  k_scan_add<<<nt, kThreads, 0, s>>>(out, len, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                      double mass_scalar) {
+  Workspace& W = P->ws;
+  hipStream_t s = P->stream;
+  hipError_t e = launch_fill_i32(W.count, P->ncell, 0, s);
+  if (e != hipSuccess) return e;
+  k_bin_count<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, pos, P->ng, P->lg, 1.0 / P->h,
+                                                           W.key, W.rank, W.count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan(W.count, W.start, P->ncell, W.scan_tmp, s)) != hipSuccess) return e;
+  if (P->prm.precision == P3M_FP32)
+    k_scatter<float><<<blocks_for(n, kThreads), kThreads, 0, s>>>(
+        n, pos, mass, mass_scalar, P->ng, P->lg, P->h, W.key, W.rank, W.start, W.perm,
+        W.skey, (float4*)W.rec);
+  else
+    k_scatter<double><<<blocks_for(n, kThreads), kThreads, 0, s>>>(
+        n, pos, mass, mass_scalar, P->ng, P->lg, P->h, W.key, W.rank, W.start, W.perm,
+        W.skey, (double4*)W.rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_items(p3m_plan* P) {
+  Workspace& W = P->ws;
+  hipStream_t s = P->stream;
+  k_group_chunks<<<blocks_for(P->ngroup, kThreads), kThreads, 0, s>>>(
+      W.start, P->ng, P->lg, P->G, P->lgG, P->ngroup, W.gchunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_scan(W.gchunk, W.goff, P->ngroup, W.scan_tmp, s)) != hipSuccess) return e;
+  k_emit_items<<<blocks_for(P->ngroup, kThreads), kThreads, 0, s>>>(W.gchunk, W.goff,
+                                                                    P->ngroup, W.items);
+  return hipGetLastError();
+}
+
+}  // namespace p3m

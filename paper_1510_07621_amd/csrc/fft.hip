@@ -1,0 +1,316 @@
+// Hand-written 3-D real-to-complex FFT Poisson solve on the PM grid.
+//
+// Layout: the real grid is [x][y][z] (z fastest, ng^3 values); the spectrum
+// is [kx][ky][kz] with kz = 0..ng/2 (ng * ng * (ng/2 + 1) complex values).
+// Five passes, each reading and writing the grid once, every transform done
+// in LDS:
+//   1. z, real -> complex: each z-line of ng reals is transformed as ng/2
+//      complex values (even samples real, odd samples imaginary) and the
+//      ng/2 + 1 outputs are separated with the usual split step;
+//   2. y, complex forward;
+//   3. x, complex forward, multiply by the Green's function, x inverse (fused);
+//   4. y, complex inverse;
+//   5. z, complex -> real (the split step in reverse, then ng/2 complex inverse).
+// Transforms are radix-2: decimation in time (bit-reversed input, natural
+// output) forward and decimation in frequency (natural input, bit-reversed
+// output) inverse, so no pass needs a separate reordering step. All
+// transforms are unnormalised; the 1/ng^3 of the inverse is folded into the
+// Green's function
+//     G(k) = -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^p) / ng^3,  G(0) = 0,
+//     W(k) = prod_d sinc^2(pi n_d / ng),  k = 2 pi n / box,
+// which is separable apart from 1/k^2: G = c * e(nx) e(ny) e(nz) / (k2(nx) +
+// k2(ny) + k2(nz)) with per-axis tables e(n) = exp(-k_n^2 r_s^2) / W1(n)^p and
+// k2(n) = k_n^2, built once per plan.
+#include "p3m_internal.h"
+
+namespace p3m {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kLdsElems = 2048;   // complex values staged per block
+
+template <typename T2>
+__device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+  T2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+__device__ __forceinline__ int brev(int v, int bits) {
+  return bits ? (int)(__brev((unsigned)v) >> (32 - bits)) : 0;
+}
+
+// nb independent length-len transforms in buf (contiguous, buf[b*len + i]).
+// Twiddles: tw[k] = exp(-2 pi i k / twn), k < twn/2; inverse uses conjugates.
+template <typename T, bool INV>
+__device__ void fft_dit(typename Vec<T>::v2* buf, int nb, int len, int lglen,
+                        const typename Vec<T>::v2* __restrict__ tw, int twn) {
+  const int halfn = len >> 1;
+  for (int lh = 0; lh < lglen; ++lh) {
+    const int half = 1 << lh;
+    const int tstride = twn >> (lh + 1);
+    for (int q = threadIdx.x; q < nb * halfn; q += blockDim.x) {
+      int b = q >> (lglen - 1), r = q & (halfn - 1);
+      int j = r & (half - 1);
+      int i0 = ((r - j) << 1) + j, i1 = i0 + half;
+      typename Vec<T>::v2 w = tw[j * tstride];
+      if (INV) w.y = -w.y;
+      typename Vec<T>::v2* p = buf + b * len;
+      typename Vec<T>::v2 a = p[i0], c = cmul(p[i1], w);
+      p[i0].x = a.x + c.x; p[i0].y = a.y + c.y;
+      p[i1].x = a.x - c.x; p[i1].y = a.y - c.y;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, bool INV>
+__device__ void fft_dif(typename Vec<T>::v2* buf, int nb, int len, int lglen,
+                        const typename Vec<T>::v2* __restrict__ tw, int twn) {
+  const int halfn = len >> 1;
+  for (int lh = lglen - 1; lh >= 0; --lh) {
+    const int half = 1 << lh;
+    const int tstride = twn >> (lh + 1);
+    for (int q = threadIdx.x; q < nb * halfn; q += blockDim.x) {
+      int b = q >> (lglen - 1), r = q & (halfn - 1);
+      int j = r & (half - 1);
+      int i0 = ((r - j) << 1) + j, i1 = i0 + half;
+      typename Vec<T>::v2 w = tw[j * tstride];
+      if (INV) w.y = -w.y;
+      typename Vec<T>::v2* p = buf + b * len;
+      typename Vec<T>::v2 a = p[i0], c = p[i1], d;
+      p[i0].x = a.x + c.x; p[i0].y = a.y + c.y;
+      d.x = a.x - c.x; d.y = a.y - c.y;
+      p[i1] = cmul(d, w);
+    }
+    __syncthreads();
+  }
+}
+
+// Pass 1: real z-lines -> half spectra. lines per block = nl.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fft_z_r2c(const T* __restrict__ grid, typename Vec<T>::v2* __restrict__ spec, int ng, int lg,
+            int nl, const typename Vec<T>::v2* __restrict__ tw) {
+  using T2 = typename Vec<T>::v2;
+  extern __shared__ unsigned char smem_raw[];
+  T2* buf = reinterpret_cast<T2*>(smem_raw);
+  const int M = ng >> 1, lgM = lg - 1;
+  const int64_t line0 = (int64_t)blockIdx.x * nl;
+  const T2* in = reinterpret_cast<const T2*>(grid);
+  for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
+    int b = idx >> lgM, m = idx & (M - 1);
+    buf[b * M + brev(m, lgM)] = in[(line0 + b) * M + m];
+  }
+  __syncthreads();
+  fft_dit<T, false>(buf, nl, M, lgM, tw, ng);
+  const int M1 = M + 1;
+  for (int idx = threadIdx.x; idx < nl * M1; idx += kThreads) {
+    int b = idx / M1, k = idx - b * M1;
+    T2 zk = buf[b * M + (k & (M - 1))];
+    T2 zc = buf[b * M + ((M - k) & (M - 1))];
+    zc.y = -zc.y;
+    // E = (Z_k + conj Z_{M-k}) / 2,  O = (Z_k - conj Z_{M-k}) / 2i
+    T2 E, O;
+    E.x = T(0.5) * (zk.x + zc.x); E.y = T(0.5) * (zk.y + zc.y);
+    O.x = T(0.5) * (zk.y - zc.y); O.y = -T(0.5) * (zk.x - zc.x);
+    T2 w;
+    if (k < M) w = tw[k]; else { w.x = T(-1); w.y = T(0); }
+    T2 wo = cmul(w, O);
+    T2 X;
+    X.x = E.x + wo.x; X.y = E.y + wo.y;
+    spec[(line0 + b) * M1 + k] = X;
+  }
+}
+
+// Pass 5: half spectra -> real z-lines (unnormalised inverse).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fft_z_c2r(const typename Vec<T>::v2* __restrict__ spec, T* __restrict__ grid, int ng, int lg,
+            int nl, const typename Vec<T>::v2* __restrict__ tw) {
+  using T2 = typename Vec<T>::v2;
+  extern __shared__ unsigned char smem_raw[];
+  T2* buf = reinterpret_cast<T2*>(smem_raw);
+  const int M = ng >> 1, lgM = lg - 1, M1 = M + 1;
+  const int64_t line0 = (int64_t)blockIdx.x * nl;
+  for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
+    int b = idx >> lgM, k = idx & (M - 1);
+    const T2* row = spec + (line0 + b) * M1;
+    T2 xk = row[k], xc = row[M - k];
+    xc.y = -xc.y;
+    // E = X_k + conj X_{M-k},  O = (X_k - conj X_{M-k}) * conj(W^k),  Z = E + i O
+    T2 E, D, w = tw[k];
+    E.x = xk.x + xc.x; E.y = xk.y + xc.y;
+    D.x = xk.x - xc.x; D.y = xk.y - xc.y;
+    w.y = -w.y;
+    T2 O = cmul(D, w);
+    T2 Z;
+    Z.x = E.x - O.y; Z.y = E.y + O.x;
+    buf[b * M + k] = Z;
+  }
+  __syncthreads();
+  fft_dif<T, true>(buf, nl, M, lgM, tw, ng);
+  T2* out = reinterpret_cast<T2*>(grid);
+  for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
+    int b = idx >> lgM, m = idx & (M - 1);
+    out[(line0 + b) * M + m] = buf[b * M + brev(m, lgM)];
+  }
+}
+
+// Pass 2 / 4: complex transform along y for one x-plane and a chunk of kc
+// kz-columns.
+template <typename T, bool INV>
+__global__ void __launch_bounds__(kThreads)
+k_fft_y(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
+        const typename Vec<T>::v2* __restrict__ tw) {
+  using T2 = typename Vec<T>::v2;
+  extern __shared__ unsigned char smem_raw[];
+  T2* buf = reinterpret_cast<T2*>(smem_raw);
+  const int M1 = (ng >> 1) + 1;
+  const int nchunk = (M1 + kc - 1) / kc;
+  const int x = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
+  const int kn = min(kc, M1 - kz0);
+  T2* plane = spec + (int64_t)x * ng * M1 + kz0;
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    int y = idx / kc, c = idx - y * kc;
+    T2 v;
+    if (c < kn) v = plane[(int64_t)y * M1 + c]; else { v.x = T(0); v.y = T(0); }
+    buf[c * ng + (INV ? y : brev(y, lg))] = v;
+  }
+  __syncthreads();
+  if (INV) fft_dif<T, true>(buf, kc, ng, lg, tw, ng);
+  else fft_dit<T, false>(buf, kc, ng, lg, tw, ng);
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    int y = idx / kc, c = idx - y * kc;
+    if (c < kn) plane[(int64_t)y * M1 + c] = buf[c * ng + (INV ? brev(y, lg) : y)];
+  }
+}
+
+// Pass 3: forward x transform, Green's function, inverse x transform, for one
+// y-row and a chunk of kc kz-columns.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
+              const typename Vec<T>::v2* __restrict__ tw, const T* __restrict__ etab,
+              const T* __restrict__ k2tab, T gconst) {
+  using T2 = typename Vec<T>::v2;
+  extern __shared__ unsigned char smem_raw[];
+  T2* buf = reinterpret_cast<T2*>(smem_raw);
+  const int M1 = (ng >> 1) + 1;
+  const int nchunk = (M1 + kc - 1) / kc;
+  const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
+  const int kn = min(kc, M1 - kz0);
+  const int64_t xs = (int64_t)ng * M1;
+  T2* col = spec + (int64_t)y * M1 + kz0;
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    int x = idx / kc, c = idx - x * kc;
+    T2 v;
+    if (c < kn) v = col[x * xs + c]; else { v.x = T(0); v.y = T(0); }
+    buf[c * ng + brev(x, lg)] = v;
+  }
+  __syncthreads();
+  fft_dit<T, false>(buf, kc, ng, lg, tw, ng);
+  const T ey = etab[y], k2y = k2tab[y];
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    int c = idx >> lg, kx = idx & (ng - 1);
+    int kz = kz0 + c;
+    T g = T(0);
+    if (c < kn) {
+      T k2 = k2tab[kx] + k2y + k2tab[kz];
+      if (k2 > T(0)) g = gconst * etab[kx] * ey * etab[kz] / k2;
+    }
+    T2 v = buf[idx];
+    v.x *= g; v.y *= g;
+    buf[idx] = v;
+  }
+  __syncthreads();
+  fft_dif<T, true>(buf, kc, ng, lg, tw, ng);
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    int x = idx / kc, c = idx - x * kc;
+    if (c < kn) col[x * xs + c] = buf[c * ng + brev(x, lg)];
+  }
+}
+
+template <typename T>
+__global__ void k_tables(int ng, double box, double r_s, int deconv_power,
+                         typename Vec<T>::v2* __restrict__ tw, T* __restrict__ etab,
+                         T* __restrict__ k2tab) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  if (i < ng / 2) {
+    double s, c;
+    sincospi(2.0 * i / ng, &s, &c);
+    typename Vec<T>::v2 w;
+    w.x = (T)c; w.y = (T)(-s);
+    tw[i] = w;
+  }
+  int n = i < ng / 2 ? i : i - ng;
+  double k = 2.0 * M_PI * n / box;
+  double sinc = n == 0 ? 1.0 : sinpi((double)n / ng) / (M_PI * (double)n / ng);
+  double w1 = sinc * sinc;
+  double e = exp(-k * k * r_s * r_s);
+  for (int p = 0; p < deconv_power; ++p) e /= w1;
+  etab[i] = (T)e;
+  k2tab[i] = (T)(k * k);
+}
+
+// Largest power of two <= v (v >= 1).
+inline int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_tables(p3m_plan* P) {
+  Workspace& W = P->ws;
+  int ng = P->ng;
+  T* etab = (T*)W.gtab;
+  k_tables<T><<<(ng + 255) / 256, 256, 0, P->stream>>>(ng, P->prm.box, P->r_s,
+                                                        P->prm.deconv_power,
+                                                        (typename Vec<T>::v2*)W.twiddle, etab,
+                                                        etab + ng);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_poisson(p3m_plan* P) {
+  using T2 = typename Vec<T>::v2;
+  Workspace& W = P->ws;
+  const int ng = P->ng, lg = P->lg, M = ng / 2, M1 = M + 1;
+  const T2* tw = (const T2*)W.twiddle;
+  T2* spec = (T2*)W.spec;
+  T* grid = (T*)W.grid;
+  hipStream_t s = P->stream;
+  // z passes: nl lines per block
+  int nl = pow2_floor(kLdsElems / M);
+  if (nl > ng * ng) nl = ng * ng;
+  size_t lds_z = (size_t)nl * M * sizeof(T2);
+  unsigned blocks_z = (unsigned)((int64_t)ng * ng / nl);
+  // y / x passes: kc kz-columns per block
+  int kc = kLdsElems / ng;
+  if (kc > 16) kc = 16;
+  if (kc < 1) kc = 1;
+  size_t lds_c = (size_t)kc * ng * sizeof(T2);
+  unsigned nchunk = (unsigned)((M1 + kc - 1) / kc);
+  const T* etab = (const T*)W.gtab;
+  T gconst = (T)(-4.0 * M_PI * P->prm.G / ((double)ng * ng * ng));
+
+  k_fft_z_r2c<T><<<blocks_z, kThreads, lds_z, s>>>(grid, spec, ng, lg, nl, tw);
+  k_fft_y<T, false><<<ng * nchunk, kThreads, lds_c, s>>>(spec, ng, lg, kc, tw);
+  k_fft_x_green<T><<<ng * nchunk, kThreads, lds_c, s>>>(spec, ng, lg, kc, tw, etab,
+                                                        etab + ng, gconst);
+  k_fft_y<T, true><<<ng * nchunk, kThreads, lds_c, s>>>(spec, ng, lg, kc, tw);
+  k_fft_z_c2r<T><<<blocks_z, kThreads, lds_z, s>>>(spec, grid, ng, lg, nl, tw);
+  return hipGetLastError();
+}
+
+template hipError_t launch_tables<float>(p3m_plan*);
+template hipError_t launch_tables<double>(p3m_plan*);
+template hipError_t launch_fft_poisson<float>(p3m_plan*);
+template hipError_t launch_fft_poisson<double>(p3m_plan*);
+
+}  // namespace p3m

@@ -1,0 +1,398 @@
+// The C ABI of libp3m.so: argument checking, plan geometry and workspace,
+// and the order of the force stages. Declared in include/p3m.h and
+// include/p3m_host.h.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "p3m_internal.h"
+
+using namespace p3m;
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t{1} << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// Minimum gap, in whole cells, between an i-group spanning cells [0, g) of
+// one axis and the cell at offset d.
+int axis_gap(int d, int g) {
+  if (d < 0) return -d - 1;
+  if (d >= g) return d - g;
+  return 0;
+}
+
+template <typename T>
+T* dev_alloc(size_t count, hipError_t& err) {
+  void* p = nullptr;
+  if (err != hipSuccess) return nullptr;
+  size_t bytes = count * sizeof(T);
+  if (bytes == 0) bytes = 256;
+  err = hipMalloc(&p, bytes);
+  return err == hipSuccess ? (T*)p : nullptr;
+}
+
+void free_workspace(p3m_plan* P) {
+  Workspace& W = P->ws;
+  void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
+                  W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
+                  W.spec, W.twiddle, W.gtab,  W.counter};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  W = Workspace{};
+  if (P->events_ready)
+    for (auto& e : P->ev) (void)hipEventDestroy(e);
+  P->events_ready = false;
+}
+
+int status_of(hipError_t e) {
+  if (e == hipSuccess) return P3M_OK;
+  if (e == hipErrorOutOfMemory) return P3M_ENOMEM;
+  return P3M_EHIP;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!a || !b) return false;
+  auto pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+struct StageTimer {
+  p3m_plan* P;
+  int stage;
+  StageTimer(p3m_plan* p, int s) : P(p), stage(s) {
+    if (P->timing) (void)hipEventRecord(P->ev[2 * stage], P->stream);
+  }
+  ~StageTimer() {
+    if (P->timing) {
+      (void)hipEventRecord(P->ev[2 * stage + 1], P->stream);
+      P->ran[stage] = true;
+    }
+  }
+};
+
+enum class Part { kP3M, kPM, kPP };
+
+template <typename T>
+hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                     double ms, void* force, int f32, Part part) {
+  hipError_t e;
+  {
+    StageTimer t(P, P3M_STAGE_BIN);
+    if ((e = launch_bin(P, n, pos, mass, ms)) != hipSuccess) return e;
+    if (part != Part::kPM && (e = launch_items(P)) != hipSuccess) return e;
+  }
+  if (part != Part::kPP) {
+    {
+      StageTimer t(P, P3M_STAGE_DEPOSIT);
+      if ((e = launch_deposit<T>(P)) != hipSuccess) return e;
+    }
+    {
+      StageTimer t(P, P3M_STAGE_FFT);
+      if ((e = launch_fft_poisson<T>(P)) != hipSuccess) return e;
+    }
+    {
+      StageTimer t(P, P3M_STAGE_INTERP);
+      if ((e = launch_interp<T>(P, n, part == Part::kPM ? force : nullptr, f32)) != hipSuccess)
+        return e;
+    }
+  }
+  if (part != Part::kPM) {
+    StageTimer t(P, P3M_STAGE_PP);
+    if ((e = launch_pairs<T>(P, n, part == Part::kP3M, force, f32)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int force_entry(p3m_plan* P, int64_t n, const double* pos, const double* mass, double ms,
+                void* force, int32_t f32, Part part) {
+  if (!P || n < 0 || n > P->n_max) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!pos || !force) return P3M_EINVAL;
+  if (!mass && !std::isfinite(ms)) return P3M_EINVAL;
+  size_t fbytes = (size_t)(3 * n) * (f32 ? sizeof(float) : sizeof(double));
+  if (overlaps(force, fbytes, pos, (size_t)(3 * n) * sizeof(double)) ||
+      overlaps(force, fbytes, mass, (size_t)n * sizeof(double)))
+    return P3M_EINVAL;
+  for (bool& r : P->ran) r = false;
+  hipError_t e = P->prm.precision == P3M_FP32
+                     ? run_force<float>(P, n, pos, mass, ms, force, f32 ? 1 : 0, part)
+                     : run_force<double>(P, n, pos, mass, ms, force, f32 ? 1 : 0, part);
+  return status_of(e);
+}
+
+}  // namespace
+
+namespace p3m {
+
+int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
+  if (g < 1 || !(radius_cells > 0) || !std::isfinite(radius_cells)) return P3M_EINVAL;
+  // A cell can hold a partner closer than r_c iff its gap to the group box is
+  // below r_c; the small margin keeps rounding in the pair test harmless.
+  const double R = radius_cells + 1e-9;
+  const double R2 = R * R;
+  const int reach = (int)std::ceil(R) + 1;
+  int count = 0;
+  for (int dx = -reach; dx < g + reach; ++dx) {
+    int gx = axis_gap(dx, g);
+    for (int dy = -reach; dy < g + reach; ++dy) {
+      int gy = axis_gap(dy, g);
+      double gxy = double(gx) * gx + double(gy) * gy;
+      if (!(gxy < R2)) continue;
+      int lo = 0, hi = -1;
+      for (int dz = -reach; dz < g + reach; ++dz) {
+        int gz = axis_gap(dz, g);
+        if (gxy + double(gz) * gz < R2) {
+          if (hi < lo) lo = dz;
+          hi = dz;
+        }
+      }
+      if (count < cap && out) {
+        out[4 * count + 0] = dx;
+        out[4 * count + 1] = dy;
+        out[4 * count + 2] = lo;
+        out[4 * count + 3] = hi;
+      }
+      ++count;
+    }
+  }
+  return count;
+}
+
+}  // namespace p3m
+
+extern "C" {
+
+int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out, int32_t cap) {
+  if (cap < 0 || (cap > 0 && !rows_out)) return P3M_EINVAL;
+  return p3m::stencil_rows(g, radius_cells, rows_out, cap);
+}
+
+int32_t p3m_group_edge(int64_t n, int32_t grid_n) {
+  if (n <= 0 || grid_n < 2) return 1;
+  double cells_per_particle = std::pow((double)grid_n, 3) / (double)n;
+  int best = 1;
+  double best_err = 1e300;
+  for (int g = 1; g <= 4 && g <= grid_n / 2; g *= 2) {
+    double mean = (double)g * g * g / cells_per_particle;
+    double err = std::fabs(std::log(mean / 8.0));
+    if (err < best_err) {
+      best_err = err;
+      best = g;
+    }
+  }
+  return best;
+}
+
+int p3m_params_default(p3m_params* out, int32_t grid_n, double box) {
+  if (!out) return P3M_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->grid_n = grid_n;
+  out->precision = P3M_FP32;
+  out->fd_order = 4;
+  out->deconv_power = 2;
+  out->box = box;
+  out->rs_cells = 1.25;
+  out->cutoff_rs = 4.5;
+  out->softening = 0.0;
+  out->G = 1.0;
+  return P3M_OK;
+}
+
+int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_plan** out) {
+  if (!prm || !out) return P3M_EINVAL;
+  const p3m_params& q = *prm;
+  if (!is_pow2(q.grid_n) || q.grid_n < 16 || q.grid_n > 512) return P3M_EINVAL;
+  if (q.precision != P3M_FP64 && q.precision != P3M_FP32) return P3M_EINVAL;
+  if (q.fd_order != 2 && q.fd_order != 4) return P3M_EINVAL;
+  if (q.deconv_power != 0 && q.deconv_power != 2) return P3M_EINVAL;
+  if (!(q.box > 0) || !std::isfinite(q.box)) return P3M_EINVAL;
+  if (!(q.rs_cells > 0) || !std::isfinite(q.rs_cells)) return P3M_EINVAL;
+  if (!(q.cutoff_rs > 0) || !std::isfinite(q.cutoff_rs)) return P3M_EINVAL;
+  if (!(q.softening >= 0) || !std::isfinite(q.softening)) return P3M_EINVAL;
+  if (!std::isfinite(q.G)) return P3M_EINVAL;
+  if (n_max < 0 || n_max >= (int64_t{1} << 31)) return P3M_EINVAL;
+  const double h = q.box / q.grid_n;
+  const double r_s = q.rs_cells * h;
+  const double r_c = q.cutoff_rs * r_s;
+  if (!(r_c < 0.5 * q.box)) return P3M_ERANGE;
+
+  p3m_plan* P = new (std::nothrow) p3m_plan;
+  if (!P) return P3M_ENOMEM;
+  P->prm = q;
+  P->n_max = n_max;
+  P->stream = (hipStream_t)hip_stream;
+  P->ng = q.grid_n;
+  P->lg = ilog2(q.grid_n);
+  P->ncell = (int64_t)q.grid_n * q.grid_n * q.grid_n;
+  P->h = h;
+  P->r_s = r_s;
+  P->r_c = r_c;
+  P->eps = q.softening;
+  P->G = p3m_group_edge(n_max, q.grid_n);
+  P->lgG = ilog2(P->G);
+  P->ngd = q.grid_n / P->G;
+  P->ngroup = (int64_t)P->ngd * P->ngd * P->ngd;
+  P->nrows = stencil_rows(P->G, r_c / h, nullptr, 0);
+  P->max_items = P->ngroup + (n_max + 63) / 64;
+  const int64_t nspec = (int64_t)q.grid_n * q.grid_n * (q.grid_n / 2 + 1);
+  const size_t real = q.precision == P3M_FP32 ? sizeof(float) : sizeof(double);
+  const int64_t nn = n_max > 0 ? n_max : 1;
+  P->scan_tmp_len = scan_tmp_size(P->ncell > P->ngroup ? P->ncell : P->ngroup);
+
+  hipError_t err = hipGetDevice(&P->device);
+  Workspace& W = P->ws;
+  W.key = dev_alloc<int32_t>(nn, err);
+  W.rank = dev_alloc<int32_t>(nn, err);
+  W.count = dev_alloc<int32_t>(P->ncell + 1, err);
+  W.start = dev_alloc<int32_t>(P->ncell + 1, err);
+  W.perm = dev_alloc<int32_t>(nn, err);
+  W.skey = dev_alloc<int32_t>(nn, err);
+  W.scan_tmp = dev_alloc<int32_t>(P->scan_tmp_len, err);
+  W.gchunk = dev_alloc<int32_t>(P->ngroup + 1, err);
+  W.goff = dev_alloc<int32_t>(P->ngroup + 1, err);
+  W.items = dev_alloc<int2>(P->max_items, err);
+  W.rows = dev_alloc<int4>(P->nrows, err);
+  W.rec = dev_alloc<unsigned char>(nn * 4 * real, err);
+  W.acc_pm = dev_alloc<unsigned char>(nn * 4 * real, err);
+  W.grid = dev_alloc<unsigned char>(P->ncell * real, err);
+  W.spec = dev_alloc<unsigned char>(nspec * 2 * real, err);
+  W.twiddle = dev_alloc<unsigned char>((q.grid_n / 2) * 2 * real, err);
+  W.gtab = dev_alloc<unsigned char>(2 * q.grid_n * real, err);
+  W.counter = dev_alloc<unsigned long long>(1, err);
+  if (err == hipSuccess) {
+    int32_t* rows = new (std::nothrow) int32_t[4 * (size_t)P->nrows];
+    if (!rows) {
+      free_workspace(P);
+      delete P;
+      return P3M_ENOMEM;
+    }
+    stencil_rows(P->G, r_c / h, rows, P->nrows);
+    err = hipMemcpy(W.rows, rows, sizeof(int4) * P->nrows, hipMemcpyHostToDevice);
+    delete[] rows;
+  }
+  if (err == hipSuccess)
+    err = q.precision == P3M_FP32 ? launch_tables<float>(P) : launch_tables<double>(P);
+  if (err == hipSuccess) err = hipStreamSynchronize(P->stream);
+  if (err != hipSuccess) {
+    free_workspace(P);
+    delete P;
+    return status_of(err);
+  }
+  *out = P;
+  return P3M_OK;
+}
+
+int p3m_plan_destroy(p3m_plan* P) {
+  if (!P) return P3M_OK;
+  hipError_t e = hipStreamSynchronize(P->stream);
+  free_workspace(P);
+  delete P;
+  return status_of(e);
+}
+
+int p3m_plan_set_stream(p3m_plan* P, void* hip_stream) {
+  if (!P) return P3M_EINVAL;
+  P->stream = (hipStream_t)hip_stream;
+  return P3M_OK;
+}
+
+int p3m_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+              double mass_scalar, void* force, int32_t force_fp32) {
+  return force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kP3M);
+}
+
+int pm_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+             double mass_scalar, void* force, int32_t force_fp32) {
+  return force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kPM);
+}
+
+int pp_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+             double mass_scalar, void* force, int32_t force_fp32) {
+  return force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kPP);
+}
+
+int p3m_pair_count(p3m_plan* P, int64_t n, const double* pos, int64_t* count_out) {
+  if (!P || n < 0 || n > P->n_max || !count_out) return P3M_EINVAL;
+  if (n > 0 && !pos) return P3M_EINVAL;
+  hipError_t e;
+  if (n == 0) return status_of(launch_fill_i32((int32_t*)count_out, 2, 0, P->stream));
+  for (bool& r : P->ran) r = false;
+  if ((e = launch_bin(P, n, pos, nullptr, 1.0)) != hipSuccess) return status_of(e);
+  if ((e = launch_items(P)) != hipSuccess) return status_of(e);
+  e = P->prm.precision == P3M_FP32 ? launch_pair_count<float>(P, n, count_out)
+                                   : launch_pair_count<double>(P, n, count_out);
+  return status_of(e);
+}
+
+int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32, double c_kick,
+             void* hip_stream) {
+  if (n < 0) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!mom || !force || !std::isfinite(c_kick)) return P3M_EINVAL;
+  return status_of(launch_kick(n, mom, force, force_fp32 ? 1 : 0, c_kick,
+                               (hipStream_t)hip_stream));
+}
+
+int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
+              double mass_scalar, double c_drift, double box, void* hip_stream) {
+  if (n < 0) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!pos || !mom || !(box > 0) || !std::isfinite(box) || !std::isfinite(c_drift))
+    return P3M_EINVAL;
+  if (!mass && !(mass_scalar != 0 && std::isfinite(mass_scalar))) return P3M_EINVAL;
+  return status_of(launch_drift(n, pos, mom, mass, mass_scalar, c_drift, box,
+                                (hipStream_t)hip_stream));
+}
+
+int p3m_set_timing(p3m_plan* P, int32_t enable) {
+  if (!P) return P3M_EINVAL;
+  if (enable && !P->events_ready) {
+    for (int i = 0; i < 2 * P3M_NUM_STAGES; ++i) {
+      hipError_t e = hipEventCreate(&P->ev[i]);
+      if (e != hipSuccess) {
+        for (int k = 0; k < i; ++k) (void)hipEventDestroy(P->ev[k]);
+        return status_of(e);
+      }
+    }
+    P->events_ready = true;
+  }
+  P->timing = enable != 0;
+  for (bool& r : P->ran) r = false;
+  return P3M_OK;
+}
+
+int p3m_stage_times(p3m_plan* P, double* ms_out, int32_t n_stages) {
+  if (!P || !ms_out || n_stages < 0) return P3M_EINVAL;
+  hipError_t e = hipStreamSynchronize(P->stream);
+  if (e != hipSuccess) return status_of(e);
+  for (int s = 0; s < n_stages; ++s) {
+    ms_out[s] = 0.0;
+    if (s < P3M_NUM_STAGES && P->events_ready && P->ran[s]) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, P->ev[2 * s], P->ev[2 * s + 1]);
+      if (e != hipSuccess) return status_of(e);
+      ms_out[s] = ms;
+    }
+  }
+  return P3M_OK;
+}
+
+const char* p3m_strerror(int status) {
+  switch (status) {
+    case P3M_OK: return "success";
+    case P3M_EINVAL: return "invalid argument";
+    case P3M_ENOMEM: return "out of device memory";
+    case P3M_EHIP: return "HIP runtime error";
+    case P3M_ERANGE: return "cutoff must be below half the box (minimum image)";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal declarations shared by the translation units of libp3m.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "p3m.h"
+#include "p3m_host.h"
+
+namespace p3m {
+
+// Vector types for the two arithmetic precisions of the force path.
+template <typename T> struct Vec;
+template <> struct Vec<float> {
+  using v2 = float2;
+  using v4 = float4;
+};
+template <> struct Vec<double> {
+  using v2 = double2;
+  using v4 = double4;
+};
+
+constexpr int kPairCap = 512;     // j-particles staged in LDS per pass of the pair loop
+constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
+
+// One particle in cell order: offsets from its cell's lower corner and mass.
+// (x, y, z, m) as float4 (FP32 path) or double4 (FP64 path).
+
+struct Workspace {
+  int32_t* key = nullptr;       // [n_max]   cell index per particle (input order)
+  int32_t* rank = nullptr;      // [n_max]   rank inside its cell
+  int32_t* count = nullptr;     // [ncell+1] particles per cell
+  int32_t* start = nullptr;     // [ncell+1] first sorted slot of each cell; start[ncell] = n
+  int32_t* perm = nullptr;      // [n_max]   sorted slot -> input index
+  int32_t* skey = nullptr;      // [n_max]   cell index per sorted slot
+  int32_t* scan_tmp = nullptr;  // block sums of the scans
+  int32_t* gchunk = nullptr;    // [ngroup+1] 64-particle chunks per i-group
+  int32_t* goff = nullptr;      // [ngroup+1] exclusive scan of gchunk; goff[ngroup] = items
+  int2* items = nullptr;        // [max_items] (group, chunk) work items of the pair loop
+  int4* rows = nullptr;         // [nrows]   neighbour stencil of an i-group
+  void* rec = nullptr;          // [n_max]   sorted particle records (T4)
+  void* acc_pm = nullptr;       // [n_max]   PM acceleration in sorted order (T4)
+  void* grid = nullptr;         // [ng^3]    real grid (density, then potential)
+  void* spec = nullptr;         // [ng*ng*(ng/2+1)] half-complex spectrum (T2)
+  void* twiddle = nullptr;      // [ng/2]    exp(-2 pi i k / ng) (T2)
+  void* gtab = nullptr;         // [2*ng]    Green's function factor tables (T)
+  unsigned long long* counter = nullptr;  // [1] pair-count scratch
+};
+
+}  // namespace p3m
+
+struct p3m_plan {
+  p3m_params prm{};
+  int64_t n_max = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // geometry
+  int ng = 0, lg = 0;           // grid cells per side and its log2
+  int64_t ncell = 0;
+  double h = 0, r_s = 0, r_c = 0, eps = 0;
+  int G = 2, lgG = 1;           // i-group edge in cells and its log2
+  int ngd = 0;                  // i-groups per side
+  int64_t ngroup = 0;
+  int nrows = 0;
+  int64_t max_items = 0;
+  int scan_tmp_len = 0;
+  p3m::Workspace ws;
+  // stage timers
+  bool timing = false;
+  bool events_ready = false;
+  hipEvent_t ev[2 * P3M_NUM_STAGES] = {};
+  bool ran[P3M_NUM_STAGES] = {};
+};
+
+namespace p3m {
+
+// Launchers (each enqueues on plan->stream; returns hipSuccess or the error).
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp,
+                       hipStream_t s);
+int scan_tmp_size(int64_t len);
+
+hipError_t launch_bin(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                      double mass_scalar);
+hipError_t launch_items(p3m_plan* P);
+
+template <typename T>
+hipError_t launch_deposit(p3m_plan* P);
+template <typename T>
+hipError_t launch_fft_poisson(p3m_plan* P);
+template <typename T>
+hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32);
+template <typename T>
+hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out,
+                        int force_fp32);
+template <typename T>
+hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
+template <typename T>
+hipError_t launch_tables(p3m_plan* P);
+
+hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,
+                       hipStream_t s);
+hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double* mass,
+                        double ms, double c, double box, hipStream_t s);
+
+// Host geometry helpers.
+int stencil_rows(int g, double radius_cells, int32_t* out, int cap);
+
+}  // namespace p3m

@@ -1,0 +1,58 @@
+// Kick and drift: the two particle updates of a leapfrog step, in FP64.
+//
+//   kick:  p <- p + c_kick F
+//   drift: x <- wrap(x + c_drift (p / m)),  wrap(y) = y - box floor(y / box),
+//          a result equal to box becomes 0
+//
+// Every product, quotient, sum and difference is a single correctly rounded
+// IEEE double operation in this order (explicit _rn intrinsics, so the
+// compiler cannot fuse them), which makes the updates reproducible bit for bit
+// on any IEEE implementation that performs the same operations.
+#include "p3m_internal.h"
+
+namespace p3m {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename F>
+__global__ void k_kick(int64_t n, double* __restrict__ mom, const F* __restrict__ force,
+                       double c) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  mom[i] = __dadd_rn(mom[i], __dmul_rn(c, (double)force[i]));
+}
+
+__global__ void k_drift(int64_t n, double* __restrict__ pos, const double* __restrict__ mom,
+                        const double* __restrict__ mass, double mass_scalar, double c,
+                        double box) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * n) return;
+  int64_t i = k % n;
+  double m = mass ? mass[i] : mass_scalar;
+  double v = __ddiv_rn(mom[k], m);
+  double y = __dadd_rn(pos[k], __dmul_rn(c, v));
+  double w = __dsub_rn(y, __dmul_rn(box, floor(__ddiv_rn(y, box))));
+  pos[k] = (w >= box) ? 0.0 : w;
+}
+
+}  // namespace
+
+hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,
+                       hipStream_t s) {
+  unsigned blocks = (unsigned)((3 * n + kThreads - 1) / kThreads);
+  if (fp32)
+    k_kick<float><<<blocks, kThreads, 0, s>>>(n, mom, (const float*)force, c);
+  else
+    k_kick<double><<<blocks, kThreads, 0, s>>>(n, mom, (const double*)force, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double* mass,
+                        double ms, double c, double box, hipStream_t s) {
+  unsigned blocks = (unsigned)((3 * n + kThreads - 1) / kThreads);
+  k_drift<<<blocks, kThreads, 0, s>>>(n, pos, mom, mass, ms, c, box);
+  return hipGetLastError();
+}
+
+}  // namespace p3m

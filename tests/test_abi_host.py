@@ -1,0 +1,154 @@
+"""Host-side checks of the C ABI (no GPU needed, nothing computed on a device).
+
+The library must load, export every function its headers declare, reject
+bad arguments before touching the GPU, and build the neighbour stencil the
+pair sum relies on.
+"""
+import ctypes
+import itertools
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1510_07621_amd", "libp3m.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB),
+                                reason="libp3m.so not built (run __graft_entry__.build())")
+
+
+def _declared_functions():
+    names = set()
+    for h in ("p3m.h", "p3m_host.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w ]*?[\s\*]+(\w+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_1510_07621_amd import binding
+    return binding
+
+
+def test_every_declared_function_is_exported(b):
+    names = _declared_functions()
+    assert {"p3m_force", "pm_force", "pp_force", "p3m_kick", "p3m_drift",
+            "p3m_plan_create", "p3m_plan_destroy", "p3m_strerror",
+            "p3m_stencil_rows"} <= names
+    lib = ctypes.CDLL(LIB)
+    for n in sorted(names):
+        assert hasattr(lib, n), f"{n} declared but not exported"
+
+
+def _create(b, n_max=16, **kw):
+    p = b.Params(**{"grid_n": 32, **kw}).to_c()
+    h = ctypes.c_void_p()
+    st = b._lib.p3m_plan_create(ctypes.byref(p), n_max, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(grid_n=100), -1), (dict(grid_n=8), -1), (dict(grid_n=1024), -1),
+    (dict(precision="fp32", fd_order=3), -1), (dict(deconv_power=1), -1),
+    (dict(box=0.0), -1), (dict(box=float("nan")), -1), (dict(rs_cells=-1.0), -1),
+    (dict(cutoff_rs=0.0), -1), (dict(softening=-1e-3), -1), (dict(G=float("inf")), -1),
+    (dict(grid_n=16, rs_cells=2.0, cutoff_rs=4.0), -4),       # r_c = box/2
+    (dict(grid_n=16, rs_cells=1.25, cutoff_rs=8.0), -4),
+])
+def test_plan_create_rejects_bad_parameters(b, kw, expect):
+    prec = kw.pop("precision", "fp32")
+    st, h = _create(b, precision=prec, **kw)
+    assert st == expect and not h.value
+
+
+def test_plan_create_rejects_bad_sizes_and_nulls(b):
+    assert _create(b, n_max=-1)[0] == -1
+    assert _create(b, n_max=2 ** 31)[0] == -1
+    h = ctypes.c_void_p()
+    assert b._lib.p3m_plan_create(None, 4, None, ctypes.byref(h)) == -1
+    p = b.Params(grid_n=32).to_c()
+    assert b._lib.p3m_plan_create(ctypes.byref(p), 4, None, None) == -1
+    bad = b.Params(grid_n=32, precision="fp32").to_c()
+    bad.precision = 7
+    assert b._lib.p3m_plan_create(ctypes.byref(bad), 4, None, ctypes.byref(h)) == -1
+
+
+def test_calls_on_null_plan_and_bad_arguments(b):
+    L = b._lib
+    for fn in (L.p3m_force, L.pm_force, L.pp_force):
+        assert fn(None, 10, 1, None, 1.0, 2, 0) == -1
+    assert L.p3m_pair_count(None, 1, 1, 1) == -1
+    assert L.p3m_plan_destroy(None) == 0
+    assert L.p3m_plan_set_stream(None, None) == -1
+    assert L.p3m_set_timing(None, 1) == -1
+    assert L.p3m_kick(-1, 1, 1, 0, 1.0, None) == -1
+    assert L.p3m_kick(0, None, None, 0, 1.0, None) == 0       # empty: no-op
+    assert L.p3m_kick(5, None, 1, 0, 1.0, None) == -1
+    assert L.p3m_kick(5, 1, 1, 0, float("nan"), None) == -1
+    assert L.p3m_drift(-1, 1, 1, None, 1.0, 1.0, 1.0, None) == -1
+    assert L.p3m_drift(0, None, None, None, 1.0, 1.0, 1.0, None) == 0
+    assert L.p3m_drift(5, 1, 1, None, 1.0, 1.0, 0.0, None) == -1     # box <= 0
+    assert L.p3m_drift(5, 1, 1, None, 0.0, 1.0, 1.0, None) == -1     # zero scalar mass
+    st = b._lib.p3m_stencil_rows(0, 5.0, None, 0)
+    assert st == -1
+
+
+def test_strerror(b):
+    assert b.strerror(0) == "success"
+    assert "invalid" in b.strerror(-1)
+    assert "memory" in b.strerror(-2)
+    assert "HIP" in b.strerror(-3)
+    assert "half the box" in b.strerror(-4)
+    assert b.strerror(12345) == "unknown status"
+
+
+def _gap(d, g):
+    return -d - 1 if d < 0 else (d - g if d >= g else 0)
+
+
+@pytest.mark.parametrize("g,R", [(1, 5.625), (2, 5.625), (4, 5.625), (2, 2.5), (2, 7.99),
+                                 (1, 0.3), (4, 1.0)])
+def test_stencil_rows_cover_exactly_the_cells_within_reach(b, g, R):
+    """A cell is in the stencil iff its box comes closer than R cells to the
+    g^3 group box; rows are z-runs with no overlaps."""
+    rows = b.stencil_rows(g, R)
+    got = set()
+    for dx, dy, lo, hi in rows:
+        assert lo <= hi
+        for dz in range(lo, hi + 1):
+            assert (dx, dy, dz) not in got
+            got.add((dx, dy, dz))
+    reach = math.ceil(R) + 2
+    want = set()
+    for dx, dy, dz in itertools.product(range(-reach, g + reach), repeat=3):
+        # the library keeps a 1e-9 cell margin so FP rounding cannot drop a pair
+        if _gap(dx, g) ** 2 + _gap(dy, g) ** 2 + _gap(dz, g) ** 2 < (R + 1e-9) ** 2:
+            want.add((dx, dy, dz))
+    assert got == want
+
+
+def test_stencil_contains_every_partner_cell_of_random_pairs(b):
+    """Monte Carlo: for i in the group and j within r_c, j's cell is visited."""
+    import numpy as np
+    rng = np.random.default_rng(0)
+    g, R = 2, 5.625
+    cells = {(dx, dy, dz) for dx, dy, lo, hi in b.stencil_rows(g, R) for dz in range(lo, hi + 1)}
+    xi = rng.random((20000, 3)) * g
+    d = rng.normal(size=(20000, 3))
+    d *= (rng.random(20000) ** (1 / 3) * R / np.linalg.norm(d, axis=1))[:, None]
+    xj = xi + d
+    for c in np.floor(xj).astype(int):
+        assert tuple(c) in cells
+
+
+def test_group_edge(b):
+    assert b.group_edge(128 ** 3, 128) == 2        # one particle per cell -> 8 per group
+    assert b.group_edge(16 ** 3, 128) == 4         # sparse
+    assert b.group_edge(8 * 64 ** 3, 64) == 1      # dense
+    assert b.group_edge(0, 64) == 1
+    assert b.group_edge(10 ** 9, 16) == 1

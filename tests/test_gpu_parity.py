@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Element-by-element on the same seeded inputs. Tolerances (per-particle
+relative force error, RMS over particles): FP64 path 1e-6 (checked tighter
+where the arithmetic allows), FP32 path 1e-3; the short-range sum alone is
+an exact sum reached faster, so it is held to 1e-12 (FP64) and 1e-5 (FP32).
+Integer results (pair counts) are compared exactly; kick and drift bit for
+bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ewald, integrate, metrics
+from oracle import p3m as o_p3m
+from oracle import pm as o_pm
+from oracle import pp as o_pp
+from paper_1510_07621_amd import ics
+
+from _gpu import dev, host, oracle_parts, plan, require_gpu, sample_targets, workload_positions
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _err(F, ref):
+    return metrics.force_errors(F, ref)
+
+
+# --------------------------------------------------------------- kick / drift
+
+@pytest.mark.parametrize("n", [1, 1000, 65537])
+def test_kick_bitwise(n):
+    from paper_1510_07621_amd import binding
+    rng = np.random.default_rng(n)
+    p = rng.normal(size=(3, n))
+    for fdt in (np.float64, np.float32):
+        F = rng.normal(size=(3, n)).astype(fdt)
+        pd = dev(p)
+        binding.kick(pd, dev(F, torch.float64 if fdt == np.float64 else torch.float32), 0.37)
+        assert np.array_equal(host(pd), integrate.kick(p, F, 0.37))
+
+
+@pytest.mark.parametrize("use_mass_array", [False, True])
+def test_drift_bitwise_and_wraps(use_mass_array):
+    from paper_1510_07621_amd import binding
+    n = 5000
+    rng = np.random.default_rng(3)
+    x = ics.uniform(n, 1.0, seed=3)
+    p = rng.normal(size=(3, n)) * 2.0
+    m = rng.uniform(0.5, 2.0, n) if use_mass_array else 0.75
+    xd = dev(x)
+    binding.drift(xd, dev(p), dev(m) if use_mass_array else m, 0.61, 1.0)
+    got = host(xd)
+    assert np.array_equal(got, integrate.drift(x, p, m, 0.61, 1.0))
+    assert got.min() >= 0.0 and got.max() < 1.0
+
+
+def test_drift_test_of_the_guide_crossing_faces():
+    """Equal velocities on a lattice (no net force): 20 drifts through the
+    faces equal the oracle bit for bit and the closed form to ~ulp."""
+    from paper_1510_07621_amd import binding
+    pos = ics.lattice(8, offset=0.1)
+    v = np.array([0.37, -0.81, 1.3])[:, None]
+    m = 0.5
+    mom = np.broadcast_to(v * m, pos.shape).copy()
+    xd, pd = dev(pos), dev(mom)
+    x = pos.copy()
+    for _ in range(20):
+        binding.drift(xd, pd, m, 0.173, 1.0)
+        x = integrate.drift(x, mom, m, 0.173, 1.0)
+    got = host(xd)
+    assert np.array_equal(got, x)
+    exact = integrate.wrap(pos + 20 * 0.173 * v, 1.0)
+    d = np.abs(got - exact)
+    assert np.max(np.minimum(d, 1.0 - d)) < 1e-13
+
+
+# --------------------------------------------------------------- pair counts
+
+@pytest.mark.parametrize("name,grid,n", [("uniform", 32, 32768), ("uniform", 16, 1000),
+                                         ("uniform", 64, 777)])
+def test_pair_count_exact(name, grid, n):
+    pos = ics.uniform(n, seed=grid + n)
+    rs, rc = o_p3m.params_from_cells(1.0, grid, 1.25, 4.5)
+    ref = o_pp.count_pairs(pos, 1.0, rc)
+    with plan(grid, n, "fp64") as P:
+        assert P.pair_count(dev(pos)) == ref
+    with plan(grid, n, "fp32") as P:
+        got = P.pair_count(dev(pos))
+    assert abs(got - ref) <= max(2, ref * 1e-6)     # FP32 may flip pairs at r = r_c
+
+
+# --------------------------------------------------------------- forces, small workload
+
+@pytest.fixture(scope="module")
+def uniform32():
+    w = ics.workload("uniform32")
+    pos = workload_positions("uniform32")
+    _, a_pp, a_pm = oracle_parts("uniform32")
+    return w, pos, a_pp, a_pm
+
+
+def _plan_for(w, precision):
+    return plan(w.grid_n, w.n, precision, rs_cells=w.rs_cells, cutoff_rs=w.cutoff_rs,
+                softening=w.softening, G=w.G, box=w.box)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_pp_force_parity(uniform32, precision, tol):
+    w, pos, a_pp, _ = uniform32
+    with _plan_for(w, precision) as P:
+        F = host(P.pp_force(dev(pos), w.mass))
+    e = _err(F, a_pp * w.mass)
+    assert e["rms"] <= tol, e
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_pm_force_parity(uniform32, precision, tol):
+    w, pos, _, a_pm = uniform32
+    with _plan_for(w, precision) as P:
+        F = host(P.pm_force(dev(pos), w.mass))
+    e = _err(F, a_pm * w.mass)
+    assert e["rms"] <= tol, e
+
+
+@pytest.mark.parametrize("precision,tol,tight", [("fp64", 1e-6, 1e-10), ("fp32", 1e-3, 1e-4)])
+def test_p3m_force_parity(uniform32, precision, tol, tight):
+    w, pos, a_pp, a_pm = uniform32
+    ref = (a_pp + a_pm) * w.mass
+    with _plan_for(w, precision) as P:
+        F64 = host(P.force(dev(pos), w.mass))
+        F32 = host(P.force(dev(pos), w.mass, fp32_out=True))
+    e = _err(F64, ref)
+    assert e["rms"] <= tol and e["rms"] <= tight, e
+    assert _err(F32, ref)["rms"] <= max(tol, 1e-6)
+
+
+def test_p3m_method_error_matches_the_oracle_against_ewald(uniform32):
+    """P3M vs direct Ewald: the GPU's method error equals the oracle's to
+    three significant digits (it is the same discretisation)."""
+    w, pos, a_pp, a_pm = uniform32
+    tg = sample_targets(pos, 256, seed=5)
+    truth = ewald.ewald_accel(pos, w.mass, w.box, eps=w.softening, targets=tg)
+    oracle_err = _err((a_pp + a_pm)[:, tg], truth)["rms"]
+    with _plan_for(w, "fp64") as P:
+        F = host(P.force(dev(pos), w.mass))
+    gpu_err = _err(F[:, tg] / w.mass, truth)["rms"]
+    assert 1e-3 < oracle_err < 3e-2
+    assert abs(gpu_err - oracle_err) <= 5e-4 * oracle_err
+
+
+# --------------------------------------------------------------- edge cases
+
+def test_empty_and_single_particle():
+    with plan(16, 4, "fp64") as P:
+        empty = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+        out = P.force(empty, 1.0)
+        assert out.shape == (3, 0)
+        one = dev(np.array([[0.3], [0.7], [0.11]]))
+        assert np.max(np.abs(host(P.force(one, 2.0)))) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_cell_ragged_and_masses(precision):
+    """300 particles in one cell (several 64-particle chunks), plus a ragged
+    uniform background; per-particle masses; compared with the oracle."""
+    rng = np.random.default_rng(7)
+    grid = 16
+    h = 1.0 / grid
+    dense = (np.array([5, 9, 15])[:, None] + rng.random((3, 300))) * h   # touches the z face
+    pos = np.concatenate([dense, ics.uniform(701, seed=8)], axis=1)
+    m = rng.uniform(0.5, 1.5, pos.shape[1]) / pos.shape[1]
+    eps = 0.01 * h
+    ref = o_p3m.p3m_force(pos, m, 1.0, grid, 1.25, 4.5, eps)
+    with plan(grid, pos.shape[1] + 10, precision, softening=eps) as P:
+        F = host(P.force(dev(pos), dev(m)))
+        Fs = host(P.force(dev(pos), 1.0 / pos.shape[1]))
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert _err(F, ref)["rms"] <= tol
+    ref_s = o_p3m.p3m_force(pos, 1.0 / pos.shape[1], 1.0, grid, 1.25, 4.5, eps)
+    assert _err(Fs, ref_s)["rms"] <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_positions_on_faces_and_nodes(precision):
+    grid = 32
+    h = 1.0 / grid
+    pts = np.array([[0.0, 0.0, 0.0], [1.0 - 1e-15, 0.5, 0.25], [3 * h, 7 * h, 31 * h],
+                    [0.5, 1.0 - 1e-12, 0.0], [0.999999, 0.999999, 0.999999]]).T
+    pos = np.concatenate([pts, ics.uniform(2000, seed=9)], axis=1)
+    m = 1.0 / pos.shape[1]
+    ref = o_p3m.p3m_force(pos, m, 1.0, grid, 1.25, 4.5, 1e-3)
+    with plan(grid, pos.shape[1], precision, softening=1e-3) as P:
+        F = host(P.force(dev(pos), m))
+    assert _err(F, ref)["rms"] <= (1e-10 if precision == "fp64" else 1e-4)
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lattice_zero_force_and_momentum(precision):
+    lat = ics.lattice(32)
+    n = lat.shape[1]
+    rnd = ics.uniform(n, seed=4)
+    with plan(32, n, precision, softening=1e-3) as P:
+        F = host(P.force(dev(lat), 1.0 / n))
+        Fr = host(P.force(dev(rnd), 1.0 / n))
+    scale = np.sqrt(np.mean(np.sum(Fr ** 2, axis=0)))      # typical force of a random set
+    assert np.max(np.abs(F)) < (1e-12 if precision == "fp64" else 1e-5) * scale
+    tot = np.abs(Fr.sum(axis=1)).max()                     # Newton's third law
+    assert tot < (1e-11 if precision == "fp64" else 1e-4) * np.abs(Fr).sum(axis=1).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_plane_symmetry_kick_test_of_the_guide(precision):
+    """Density varying only along x: no force along y or z."""
+    planes = ics.lattice(16)
+    planes[0] = (planes[0] + 0.02 * np.sin(2 * np.pi * planes[0])) % 1.0
+    with plan(16, planes.shape[1], precision, softening=1e-3) as P:
+        F = host(P.force(dev(planes), 1.0 / planes.shape[1]))
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert np.max(np.abs(F[1:])) <= tol * np.max(np.abs(F[0]))
+
+
+def test_permutation_invariance():
+    """The process-count invariance tests of the guide, on one GPU: the same
+    particles in another order get the same forces (to rounding)."""
+    pos = ics.uniform(8000, seed=12)
+    perm = np.random.default_rng(1).permutation(8000)
+    with plan(32, 8000, "fp64", softening=1e-3) as P:
+        F = host(P.force(dev(pos), 1.0 / 8000))
+        Fp = host(P.force(dev(pos[:, perm]), 1.0 / 8000))
+    assert _err(Fp, F[:, perm])["rms"] < 1e-12
+
+
+# --------------------------------------------------------------- full-size workloads, sampled
+
+@pytest.mark.parametrize("name,precision,tol", [
+    ("zeldovich128", "fp32", 1e-3), ("zeldovich128", "fp64", 1e-6),
+    ("plummer256", "fp32", 1e-3)])
+def test_full_size_sampled_parity(name, precision, tol):
+    w = ics.workload(name)
+    pos = workload_positions(name)
+    tg, a_pp, a_pm = oracle_parts(name, n_targets=768, seed=3)
+    ref = (a_pp + a_pm) * w.mass
+    with _plan_for(w, precision) as P:
+        F = host(P.force(dev(pos), w.mass))
+    e = _err(F[:, tg], ref)
+    print(name, precision, e)
+    assert e["rms"] <= tol, e
+    if precision == "fp64":
+        assert e["rms"] <= 1e-10, e
