@@ -5,9 +5,10 @@
 //          a result equal to box becomes 0
 //
 // Every product, quotient, sum and difference is a single correctly rounded
-// IEEE double operation in this order (explicit _rn intrinsics, so the
-// compiler cannot fuse them), which makes the updates reproducible bit for bit
-// on any IEEE implementation that performs the same operations.
+// IEEE double operation in this order (floating-point contraction is switched
+// off in these kernels, so no multiply-add is fused), which makes the updates
+// reproducible bit for bit on any IEEE implementation that performs the same
+// operations.
 #include "p3m_internal.h"
 
 namespace p3m {
@@ -18,21 +19,24 @@ constexpr int kThreads = 256;
 template <typename F>
 __global__ void k_kick(int64_t n, double* __restrict__ mom, const F* __restrict__ force,
                        double c) {
+#pragma clang fp contract(off)
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 3 * n) return;
-  mom[i] = __dadd_rn(mom[i], __dmul_rn(c, (double)force[i]));
+  double f = (double)force[i];
+  mom[i] = mom[i] + c * f;
 }
 
 __global__ void k_drift(int64_t n, double* __restrict__ pos, const double* __restrict__ mom,
                         const double* __restrict__ mass, double mass_scalar, double c,
                         double box) {
+#pragma clang fp contract(off)
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 3 * n) return;
   int64_t i = k % n;
   double m = mass ? mass[i] : mass_scalar;
-  double v = __ddiv_rn(mom[k], m);
-  double y = __dadd_rn(pos[k], __dmul_rn(c, v));
-  double w = __dsub_rn(y, __dmul_rn(box, floor(__ddiv_rn(y, box))));
+  double v = mom[k] / m;
+  double y = pos[k] + c * v;
+  double w = y - box * floor(y / box);
   pos[k] = (w >= box) ? 0.0 : w;
 }
 
