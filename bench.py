@@ -1,0 +1,204 @@
+"""Throughput of the P3M gravity step on one MI355X.
+
+A step is one kick-drift-kick leapfrog step of the whole force path:
+kick(dt/2) with the force of the previous step, drift(dt), the P3M force
+(binning, CIC deposit, FFT Poisson solve, gradient + interpolation, pair
+sum, combine) and kick(dt/2), all on one HIP stream with the particles
+resident in HBM. Workload: 128^3 particles on a Zel'dovich-displaced lattice
+(P(k) ~ k^-2, rms displacement 0.3 spacing), 128^3 PM grid, r_s = 1.25 cells,
+r_c = 4.5 r_s, Plummer softening 0.03 spacing, G = 1, FP32 force arithmetic
+with FP64 positions, momenta, kick and drift.
+
+Prints one JSON line: particles/s over the timed steps (whole job), the pair
+interaction rate of the short-range kernel, its roofline figures measured
+with HIP events around every pair-kernel launch of the timed region, the same
+step in FP64, and the CPU oracle timed on a bounded sample of the same input
+(with the force error of both GPU precisions against it).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "zeldovich128"
+FLOP_PER_PAIR = 41          # 37 FP32 arithmetic flops + 4 transcendentals per pair
+FP32_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak (needs packed FP32)
+FP64_PEAK_TFLOPS = 78.6     # MI355X published FP64 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 step timing")
+    ap.add_argument("--cpu-sample", type=int, default=20000,
+                    help="particles whose short-range force the CPU oracle evaluates")
+    return ap.parse_args()
+
+
+def run_steps(binding, plan, x, p, F, m, dt, box, steps):
+    """KDK steps; F holds the force at x on entry and on exit."""
+    for _ in range(steps):
+        binding.kick(p, F, 0.5 * dt)
+        binding.drift(x, p, m, dt, box)
+        plan.force(x, m, out=F)
+        binding.kick(p, F, 0.5 * dt)
+
+
+def time_precision(binding, torch, w, pos0, precision, steps, warmup, dt):
+    plan = binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
+                                       cutoff_rs=w.cutoff_rs, softening=w.softening,
+                                       G=w.G, precision=precision), w.n)
+    x = torch.as_tensor(pos0, device="cuda").contiguous()
+    p = torch.zeros_like(x)
+    F = torch.empty_like(x)
+    m = w.mass
+    plan.force(x, m, out=F)
+    run_steps(binding, plan, x, p, F, m, dt, w.box, warmup)
+    pairs_before = plan.pair_count(x)
+    torch.cuda.synchronize()
+    plan.set_timing(steps)
+    t0 = time.perf_counter()
+    run_steps(binding, plan, x, p, F, m, dt, w.box, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    calls, stage_ms = plan.stage_times()
+    plan.set_timing(0)
+    pairs_after = plan.pair_count(x)
+    plan.close()
+    assert calls == steps, (calls, steps)
+    return {
+        "seconds": t1 - t0,
+        "stage_ms_per_step": {k: v / steps for k, v in stage_ms.items()},
+        "pairs": 0.5 * (pairs_before + pairs_after),
+        "pairs_before": pairs_before, "pairs_after": pairs_after,
+    }
+
+
+def cpu_leg(binding, torch, w, pos, n_sample):
+    """CPU oracle timed on a bounded sample, plus the GPU force error against it."""
+    from oracle import metrics
+    from oracle import pm as o_pm
+    from oracle import pp as o_pp
+
+    rng = np.random.default_rng(77)
+    tg = np.sort(rng.choice(w.n, size=n_sample, replace=False))
+    t0 = time.perf_counter()
+    a_pm = o_pm.pm_accel(pos, w.mass, w.box, w.grid_n, w.r_s, w.G)          # all particles
+    t1 = time.perf_counter()
+    a_pp = o_pp.pp_accel(pos, w.mass, w.box, w.r_s, w.r_c, w.softening, w.G, targets=tg)
+    t2 = time.perf_counter()
+    t_pm, t_pp = t1 - t0, t2 - t1
+    t_full = t_pm + t_pp * w.n / n_sample
+    ref = (a_pp + a_pm[:, tg]) * w.mass
+    errs = {}
+    x = torch.as_tensor(pos, device="cuda")
+    for prec in ("fp32", "fp64"):
+        with binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
+                                         cutoff_rs=w.cutoff_rs, softening=w.softening,
+                                         G=w.G, precision=prec), w.n) as P:
+            F = P.force(x, w.mass)
+            torch.cuda.synchronize()
+            errs[prec] = metrics.force_errors(F.cpu().numpy()[:, tg], ref)
+    return {
+        "value": w.n / t_full,
+        "unit": "particles/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"O-PM on all {w.n} particles ({t_pm:.2f} s) + O-PP on {n_sample} "
+                   f"sampled particles ({t_pp:.2f} s), PP time scaled by N/{n_sample}; "
+                   "single-threaded NumPy/SciPy FP64"),
+        "seconds_measured": t_pm + t_pp,
+    }, errs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the force path is single-GPU; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1510_07621_amd import binding, ics
+
+    w = ics.workload(WORKLOAD)
+    pos = w.positions()
+    r32 = time_precision(binding, torch, w, pos, "fp32", args.steps, args.warmup, args.dt)
+    ms_step = 1e3 * r32["seconds"] / args.steps
+    value = w.n * args.steps / r32["seconds"]
+    pp_ms = r32["stage_ms_per_step"]["pp"]
+    pairs = r32["pairs"]
+    achieved = pairs * FLOP_PER_PAIR / (pp_ms * 1e-3) / 1e12
+    out = {
+        "metric": "P3M particles/s + pair-int/s, FP32 vs FP64 at stated force err; "
+                  "adjoint/fwd ratio",
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Zel'dovich lattice, PCG64 seed 2)",
+        "config": {
+            "workload": "zeldovich128: N=128^3 Zel'dovich-displaced lattice P(k)~k^-2 "
+                        "rms 0.3 spacing, PM grid 128^3, r_s=1.25 cells, r_c=4.5 r_s, "
+                        "eps=0.03 spacing, G=1, one KDK leapfrog step (dt=%g) per step"
+                        % args.dt,
+            "n_particles": w.n, "grid_n": w.grid_n, "precision": "fp32 force, fp64 x/p",
+        },
+        "pair_interactions_per_s": pairs / (pp_ms * 1e-3),
+        "pairs_per_step": pairs,
+        "stage_ms_per_step": r32["stage_ms_per_step"],
+        "roofline": {
+            "kernel": "k_pairs<float> (short-range pair loop)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": None,
+            "flop_per_pair": FLOP_PER_PAIR,
+            "avg_launch_ms": pp_ms,
+        },
+        "adjoint_fwd_ratio": None,
+    }
+    if not args.no_fp64:
+        r64 = time_precision(binding, torch, w, pos, "fp64", args.fp64_steps, 1, args.dt)
+        pp64 = r64["stage_ms_per_step"]["pp"]
+        out["fp64"] = {
+            "value": w.n * args.fp64_steps / r64["seconds"],
+            "ms_per_step": 1e3 * r64["seconds"] / args.fp64_steps,
+            "steps": args.fp64_steps,
+            "pair_interactions_per_s": r64["pairs"] / (pp64 * 1e-3),
+            "stage_ms_per_step": r64["stage_ms_per_step"],
+            "pp_frac_of_fp64_peak": r64["pairs"] * FLOP_PER_PAIR / (pp64 * 1e-3) / 1e12
+                                    / FP64_PEAK_TFLOPS,
+        }
+    if not args.no_cpu:
+        base, errs = cpu_leg(binding, torch, w, pos, args.cpu_sample)
+        out["cpu_baseline"] = base
+        out["force_err_vs_oracle"] = {k: {"rms": v["rms"], "max": v["max"]}
+                                      for k, v in errs.items()}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

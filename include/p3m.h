@@ -136,17 +136,22 @@ int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32,
 int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
               double mass_scalar, double c_drift, double box, void* hip_stream);
 
-/* Stage timers. When enabled, each force call records HIP events around its
- * stages on the plan's stream; p3m_stage_times then synchronises the stream
- * and writes the last call's stage durations in milliseconds (0 for stages
- * that did not run) to ms_out[0..n_stages). Stage indices: */
-#define P3M_STAGE_BIN      0  /* cell keys, counts, scan, scatter and pack   */
+/* Stage timers. p3m_set_timing(plan, capacity) with capacity > 0 records HIP
+ * events around the stages of the next `capacity` force calls, on the plan's
+ * stream and without synchronising (pm_force and pp_force record the stages
+ * they run); capacity 0 stops recording. Either call first synchronises the
+ * plan's stream and drops any earlier record. capacity <= 2^20, else EINVAL.
+ * p3m_stage_times synchronises the plan's stream, writes to ms_out[s], for
+ * s < n_stages, the total duration in milliseconds of stage s over the
+ * recorded calls (0 for a stage that never ran), and returns the number of
+ * recorded calls (>= 0) or a negative status. Stage indices: */
+#define P3M_STAGE_BIN      0  /* cell keys, counts, scan, scatter, work list  */
 #define P3M_STAGE_DEPOSIT  1  /* CIC mass deposit                              */
 #define P3M_STAGE_FFT      2  /* forward FFT, Green's function, inverse FFT   */
 #define P3M_STAGE_INTERP   3  /* finite-difference gradient + interpolation   */
 #define P3M_STAGE_PP       4  /* short-range pair loop (+ combine, unpermute) */
 #define P3M_NUM_STAGES     5
-int p3m_set_timing(p3m_plan* plan, int32_t enable);
+int p3m_set_timing(p3m_plan* plan, int32_t capacity);
 int p3m_stage_times(p3m_plan* plan, double* ms_out, int32_t n_stages);
 
 /* Static text for a status code ("unknown status" for others). */

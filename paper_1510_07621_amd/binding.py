@@ -215,13 +215,16 @@ class Plan:
                "p3m_pair_count")
         return int(cnt.item())
 
-    def set_timing(self, enable: bool = True):
-        _check(_lib.p3m_set_timing(self._handle(), 1 if enable else 0), "p3m_set_timing")
+    def set_timing(self, capacity: int):
+        """Record stage events for the next ``capacity`` force calls (0: off)."""
+        _check(_lib.p3m_set_timing(self._handle(), int(capacity)), "p3m_set_timing")
 
-    def stage_times(self) -> dict:
+    def stage_times(self):
+        """(calls recorded, {stage: total ms over those calls}); synchronises."""
         buf = (ctypes.c_double * len(STAGES))()
-        _check(_lib.p3m_stage_times(self._h, buf, len(STAGES)), "p3m_stage_times")
-        return {k: float(v) for k, v in zip(STAGES, buf)}
+        n = _lib.p3m_stage_times(self._h, buf, len(STAGES))
+        _check(min(n, 0), "p3m_stage_times")
+        return n, {k: float(v) for k, v in zip(STAGES, buf)}
 
 
 def kick(mom: torch.Tensor, force: torch.Tensor, c_kick: float) -> torch.Tensor:

@@ -46,9 +46,18 @@ void free_workspace(p3m_plan* P) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
-  if (P->events_ready)
-    for (auto& e : P->ev) (void)hipEventDestroy(e);
-  P->events_ready = false;
+}
+
+void free_timers(p3m_plan* P) {
+  if (P->ev)
+    for (int i = 0; i < P->timing_cap * 2 * P3M_NUM_STAGES; ++i)
+      if (P->ev[i]) (void)hipEventDestroy(P->ev[i]);
+  delete[] P->ev;
+  delete[] P->ran;
+  P->ev = nullptr;
+  P->ran = nullptr;
+  P->timing_cap = P->timing_calls = 0;
+  P->timing_slot = -1;
 }
 
 int status_of(hipError_t e) {
@@ -67,15 +76,23 @@ struct StageTimer {
   p3m_plan* P;
   int stage;
   StageTimer(p3m_plan* p, int s) : P(p), stage(s) {
-    if (P->timing) (void)hipEventRecord(P->ev[2 * stage], P->stream);
+    if (P->timing_slot >= 0)
+      (void)hipEventRecord(P->ev[(P->timing_slot * P3M_NUM_STAGES + stage) * 2], P->stream);
   }
   ~StageTimer() {
-    if (P->timing) {
-      (void)hipEventRecord(P->ev[2 * stage + 1], P->stream);
-      P->ran[stage] = true;
+    if (P->timing_slot >= 0) {
+      int k = P->timing_slot * P3M_NUM_STAGES + stage;
+      (void)hipEventRecord(P->ev[2 * k + 1], P->stream);
+      P->ran[k] = 1;
     }
   }
 };
+
+// Claim a timer slot for the force call about to run (if recording).
+void begin_call(p3m_plan* P) {
+  P->timing_slot = -1;
+  if (P->timing_cap > 0 && P->timing_calls < P->timing_cap) P->timing_slot = P->timing_calls++;
+}
 
 enum class Part { kP3M, kPM, kPP };
 
@@ -120,7 +137,7 @@ int force_entry(p3m_plan* P, int64_t n, const double* pos, const double* mass, d
   if (overlaps(force, fbytes, pos, (size_t)(3 * n) * sizeof(double)) ||
       overlaps(force, fbytes, mass, (size_t)n * sizeof(double)))
     return P3M_EINVAL;
-  for (bool& r : P->ran) r = false;
+  begin_call(P);
   hipError_t e = P->prm.precision == P3M_FP32
                      ? run_force<float>(P, n, pos, mass, ms, force, f32 ? 1 : 0, part)
                      : run_force<double>(P, n, pos, mass, ms, force, f32 ? 1 : 0, part);
@@ -293,6 +310,7 @@ int p3m_plan_destroy(p3m_plan* P) {
   if (!P) return P3M_OK;
   hipError_t e = hipStreamSynchronize(P->stream);
   free_workspace(P);
+  free_timers(P);
   delete P;
   return status_of(e);
 }
@@ -323,7 +341,7 @@ int p3m_pair_count(p3m_plan* P, int64_t n, const double* pos, int64_t* count_out
   if (n > 0 && !pos) return P3M_EINVAL;
   hipError_t e;
   if (n == 0) return status_of(launch_fill_i32((int32_t*)count_out, 2, 0, P->stream));
-  for (bool& r : P->ran) r = false;
+  P->timing_slot = -1;
   if ((e = launch_bin(P, n, pos, nullptr, 1.0)) != hipSuccess) return status_of(e);
   if ((e = launch_items(P)) != hipSuccess) return status_of(e);
   e = P->prm.precision == P3M_FP32 ? launch_pair_count<float>(P, n, count_out)
@@ -351,37 +369,47 @@ int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
                                 (hipStream_t)hip_stream));
 }
 
-int p3m_set_timing(p3m_plan* P, int32_t enable) {
-  if (!P) return P3M_EINVAL;
-  if (enable && !P->events_ready) {
-    for (int i = 0; i < 2 * P3M_NUM_STAGES; ++i) {
-      hipError_t e = hipEventCreate(&P->ev[i]);
-      if (e != hipSuccess) {
-        for (int k = 0; k < i; ++k) (void)hipEventDestroy(P->ev[k]);
-        return status_of(e);
-      }
-    }
-    P->events_ready = true;
+int p3m_set_timing(p3m_plan* P, int32_t capacity) {
+  if (!P || capacity < 0 || capacity > (1 << 20)) return P3M_EINVAL;
+  hipError_t e = hipStreamSynchronize(P->stream);
+  free_timers(P);
+  if (e != hipSuccess) return status_of(e);
+  if (capacity == 0) return P3M_OK;
+  const int nev = capacity * 2 * P3M_NUM_STAGES;
+  P->ev = new (std::nothrow) hipEvent_t[nev]();
+  P->ran = new (std::nothrow) unsigned char[(size_t)capacity * P3M_NUM_STAGES]();
+  if (!P->ev || !P->ran) {
+    delete[] P->ev;
+    delete[] P->ran;
+    P->ev = nullptr;
+    P->ran = nullptr;
+    return P3M_ENOMEM;
   }
-  P->timing = enable != 0;
-  for (bool& r : P->ran) r = false;
+  P->timing_cap = capacity;
+  for (int i = 0; i < nev; ++i) {
+    if ((e = hipEventCreate(&P->ev[i])) != hipSuccess) {
+      free_timers(P);
+      return status_of(e);
+    }
+  }
   return P3M_OK;
 }
 
 int p3m_stage_times(p3m_plan* P, double* ms_out, int32_t n_stages) {
-  if (!P || !ms_out || n_stages < 0) return P3M_EINVAL;
+  if (!P || (n_stages > 0 && !ms_out) || n_stages < 0) return P3M_EINVAL;
   hipError_t e = hipStreamSynchronize(P->stream);
   if (e != hipSuccess) return status_of(e);
-  for (int s = 0; s < n_stages; ++s) {
-    ms_out[s] = 0.0;
-    if (s < P3M_NUM_STAGES && P->events_ready && P->ran[s]) {
+  for (int s = 0; s < n_stages; ++s) ms_out[s] = 0.0;
+  for (int c = 0; c < P->timing_calls; ++c)
+    for (int s = 0; s < n_stages && s < P3M_NUM_STAGES; ++s) {
+      int k = c * P3M_NUM_STAGES + s;
+      if (!P->ran[k]) continue;
       float ms = 0.f;
-      e = hipEventElapsedTime(&ms, P->ev[2 * s], P->ev[2 * s + 1]);
-      if (e != hipSuccess) return status_of(e);
-      ms_out[s] = ms;
+      if ((e = hipEventElapsedTime(&ms, P->ev[2 * k], P->ev[2 * k + 1])) != hipSuccess)
+        return status_of(e);
+      ms_out[s] += ms;
     }
-  }
-  return P3M_OK;
+  return P->timing_calls;
 }
 
 const char* p3m_strerror(int status) {

@@ -66,11 +66,12 @@ struct p3m_plan {
   int64_t max_items = 0;
   int scan_tmp_len = 0;
   p3m::Workspace ws;
-  // stage timers
-  bool timing = false;
-  bool events_ready = false;
-  hipEvent_t ev[2 * P3M_NUM_STAGES] = {};
-  bool ran[P3M_NUM_STAGES] = {};
+  // stage timers: events [call][2 * stage + {0: start, 1: end}]
+  int timing_cap = 0;           // force calls that can be recorded
+  int timing_calls = 0;         // calls recorded so far
+  int timing_slot = -1;         // slot of the call in progress (-1: not recording)
+  hipEvent_t* ev = nullptr;     // [timing_cap * 2 * P3M_NUM_STAGES]
+  unsigned char* ran = nullptr; // [timing_cap * P3M_NUM_STAGES]
 };
 
 namespace p3m {
