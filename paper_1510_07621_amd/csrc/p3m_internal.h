@@ -21,7 +21,7 @@ template <> struct Vec<double> {
   using v4 = double4;
 };
 
-constexpr int kPairCap = 512;     // j-particles staged in LDS per pass of the pair loop
+constexpr int kPairCap = 256;     // j-particles staged in LDS per pass of the pair loop
 constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
 
 // One particle in cell order: offsets from its cell's lower corner and mass.

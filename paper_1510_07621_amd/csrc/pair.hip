@@ -30,6 +30,12 @@ namespace p3m {
 namespace {
 
 constexpr int kDesc = 3 * 64;       // runs per batch of 64 rows
+constexpr int kStage = kPairCap / 64;  // consecutive staged entries per lane
+template <typename T>
+constexpr int kUnroll = sizeof(T) == 4 ? 4 : 2;  // staged j read ahead per lane
+// A coordinate far outside any box: its squared separation from any real
+// particle is ~1e37, finite in FP32 and far beyond every cutoff.
+constexpr float kFar = 1e18f;
 
 template <typename T>
 struct PairArgs {
@@ -100,7 +106,7 @@ __device__ __forceinline__ int wave_inclusive(int v) {
 template <typename T, bool COUNT>
 __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
   using T4 = typename Vec<T>::v4;
-  __shared__ T4 jb[kPairCap];
+  __shared__ T4 jb[kPairCap + 1];     // + the far sentinel
   __shared__ int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
   __shared__ T d_sx[64], d_sy[64];
   __shared__ int i_lo[16], i_pre[17];
@@ -131,7 +137,8 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
     if (lane == 0) i_pre[0] = 0;
   }
   __syncthreads();
-  const int ntot = i_pre[GG];
+  // wave-uniform counts (scalar registers, so the loops below are scalar)
+  const int ntot = __builtin_amdgcn_readfirstlane(i_pre[GG]);
   const int ibeg = it.y * 64;
   const int ni = min(64, ntot - ibeg);
   const int ns = 64 / ni;
@@ -143,9 +150,9 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
   const int si = i_lo[run] + (fi - i_pre[run]);
   const T4 pi = A.rec[si];
   const int czi = A.skey[si] & mask;
-  const T xi = T(run >> lgG) * h + pi.x;
-  const T yi = T(run & (G - 1)) * h + pi.y;
-  const T zi = T(czi - gz0) * h + pi.z;
+  const T xi = active ? T(run >> lgG) * h + pi.x : kFar;
+  const T yi = active ? T(run & (G - 1)) * h + pi.y : kFar;
+  const T zi = active ? T(czi - gz0) * h + pi.z : kFar;
 
   T ax = 0, ay = 0, az = 0;
   int npairs = 0;
@@ -188,37 +195,75 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
     }
     d_sx[lane] = sx;
     d_sy[lane] = sy;
-    const int total = __shfl(inc, 63, 64);
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
     if (lane == 63) d_pre[kDesc] = total;
     __syncthreads();
 
     for (int c0 = 0; c0 < total; c0 += kPairCap) {
       const int cn = min(kPairCap, total - c0);
       if (c0 > 0) __syncthreads();
-      for (int q = lane; q < cn; q += 64) {
-        const int f = c0 + q;
-        const int d = find_desc(d_pre, f);
-        const int s = d_lo[d] + (f - d_pre[d]);
-        const T4 pj = A.rec[s];
-        const int czj = A.skey[s] & mask;
-        T4 o;
-        o.x = d_sx[d / 3] + pj.x;
-        o.y = d_sy[d / 3] + pj.y;
-        o.z = T(czj + d_zs[d]) * h + pj.z;
-        o.w = pj.w;
-        jb[q] = o;
+      // stage entries [kStage*lane, kStage*lane + kStage) of this chunk: one
+      // search for the first, a short forward walk for the rest, then all
+      // loads in flight together
+      {
+        const int q0 = kStage * lane;
+        int src[kStage], dd[kStage];
+        int d = q0 < cn ? find_desc(d_pre, c0 + q0) : 0;
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) {
+          const int f = c0 + q0 + e;
+          if (q0 + e < cn)
+            while (d_pre[d + 1] <= f) ++d;
+          dd[e] = d;
+          src[e] = q0 + e < cn ? d_lo[d] + (f - d_pre[d]) : -1;
+        }
+        T4 pj[kStage];
+        int cz[kStage];
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) {
+          if (src[e] >= 0) {
+            pj[e] = A.rec[src[e]];
+            cz[e] = A.skey[src[e]] & mask;
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) {
+          if (src[e] >= 0) {
+            const int d = dd[e];
+            T4 o;
+            o.x = d_sx[d / 3] + pj[e].x;
+            o.y = d_sy[d / 3] + pj[e].y;
+            o.z = T(cz[e] + d_zs[d]) * h + pj[e].z;
+            o.w = pj[e].w;
+            jb[q0 + e] = o;
+          }
+        }
+      }
+      if (lane == 0) {                 // a far-away sentinel after the last entry
+        T4 far;
+        far.x = far.y = far.z = -kFar;
+        far.w = T(0);
+        jb[cn] = far;
       }
       __syncthreads();
-      if (active) {
-        for (int k = st; k < cn; k += ns) {
-          const T4 pj = jb[k];
-          const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+      // lane (il, st) takes staged entries st, st + ns, ...; the trip count is
+      // wave-uniform; reads past the end hit the sentinel, and lanes without
+      // an i sit at +kFar, so both fail the cutoff test
+      const int iters = (cn + ns - 1) / ns;
+      for (int t0 = 0; t0 < iters; t0 += kUnroll<T>) {
+        T4 pj[kUnroll<T>];
+#pragma unroll
+        for (int u = 0; u < kUnroll<T>; ++u) pj[u] = jb[min(st + (t0 + u) * ns, cn)];
+#pragma unroll
+        for (int u = 0; u < kUnroll<T>; ++u) {
+          const T dx = xi - pj[u].x, dy = yi - pj[u].y, dz = zi - pj[u].z;
           const T r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < A.rc2 && r2 > T(0)) {
+          if (r2 < A.rc2) {
             if (COUNT) {
-              ++npairs;
+              npairs += r2 > T(0) ? 1 : 0;
             } else {
-              const T w = pj.w * pair_weight(r2, A.eps2, A.inv2rs);
+              T w = pj[u].w * pair_weight(r2, A.eps2, A.inv2rs);
+              w = r2 > T(0) ? w : T(0);      // zero separation: no contribution
               ax += w * dx;
               ay += w * dy;
               az += w * dz;
