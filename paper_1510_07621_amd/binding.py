@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import torch  # loads the HIP runtime the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libp3m.so")
+# P3M_LIBRARY selects another build of the same library (e.g. a debug build).
+LIB_PATH = os.environ.get("P3M_LIBRARY") or os.path.join(_HERE, "libp3m.so")
 
 P3M_OK, P3M_EINVAL, P3M_ENOMEM, P3M_EHIP, P3M_ERANGE = 0, -1, -2, -3, -4
 P3M_FP64, P3M_FP32 = 0, 1

@@ -122,7 +122,9 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
   }
   if (part != Part::kPM) {
     StageTimer t(P, P3M_STAGE_PP);
-    if ((e = launch_pairs<T>(P, n, part == Part::kP3M, force, f32)) != hipSuccess) return e;
+    if ((e = launch_pairs<T>(P, n, part == Part::kP3M, force, f32, mass == nullptr)) !=
+        hipSuccess)
+      return e;
   }
   return hipSuccess;
 }

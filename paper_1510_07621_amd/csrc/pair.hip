@@ -7,32 +7,35 @@
 // cells; a work item is (group, chunk) with up to 64 of the group's
 // particles, one wavefront per item. The j-candidates of a group are the
 // particles of every cell whose box comes closer than r_c to the group's box
-// (the stencil rows: z-runs of cells, precomputed per plan). With n_i
-// i-particles the 64 lanes form n_i x s lanes (s = 64 / n_i "streams"): lane
-// (i, stream) takes every s-th staged j, so small groups still fill the wave,
-// and the s partial sums of each i are added at the end.
+// (the stencil rows: z-runs of cells, precomputed per plan).
 //
-// Per batch of 64 stencil rows: each lane resolves one row into at most three
-// contiguous sorted runs (the z-run split where it crosses the periodic box
-// face), a wave scan flattens them, and the wave stages the runs' particles
-// into LDS (kPairCap at a time) as positions relative to the group's first
-// cell, carrying the periodic shift of the run. Positions are rebuilt from the
-// cell-relative offsets and small integer cell differences, so the FP32 path
-// never subtracts two large coordinates.
+// Lanes. Each lane holds U i-particles ("slots"), so every j it reads from
+// LDS is tested against U particles: the LDS read, not the arithmetic, is the
+// scarce resource of a cutoff test. With n_i particles the wave has
+// n_u = ceil(n_i / U) slot-sets and s = 64 / n_u streams: lane (set, stream)
+// takes every s-th staged j, so small groups still fill the wave, and the s
+// partial sums of each i are added at the end. U = 4, or 1 for an item with a
+// single particle.
 //
-// FP32 evaluation: rsq(r^2 + eps^2), sqrt(r^2), exp(-u^2), and erfc(u) from
+// Staging. Per batch of 64 stencil rows each lane resolves one row into at
+// most three contiguous sorted runs (the z-run split where it crosses the
+// periodic box face), a wave scan flattens them, and the wave stages the
+// runs' particles into LDS (kPairCap at a time) as positions relative to the
+// group's first cell, carrying the periodic shift of the run. Positions are
+// rebuilt from cell-relative offsets and small integer cell differences, so
+// the FP32 path never subtracts two large coordinates.
+//
+// Arithmetic. FP32: rsq(r^2 + eps^2), sqrt(r^2), exp(-u^2), and erfc(u) from
 // the Abramowitz & Stegun 7.1.26 rational form t P(t) exp(-u^2),
 // t = 1/(1 + p u) (absolute error <= 1.5e-7), sharing the exponential.
-// FP64 evaluation: the device library's erfc, exp, sqrt and rsqrt.
+// FP64: the device library's erfc, exp, sqrt and rsqrt.
 #include "p3m_internal.h"
 
 namespace p3m {
 namespace {
 
-constexpr int kDesc = 3 * 64;       // runs per batch of 64 rows
+constexpr int kDesc = 3 * 64;          // runs per batch of 64 rows
 constexpr int kStage = kPairCap / 64;  // consecutive staged entries per lane
-template <typename T>
-constexpr int kUnroll = sizeof(T) == 4 ? 4 : 2;  // staged j read ahead per lane
 // A coordinate far outside any box: its squared separation from any real
 // particle is ~1e37, finite in FP32 and far beyond every cutoff.
 constexpr float kFar = 1e18f;
@@ -56,7 +59,7 @@ struct PairArgs {
   unsigned long long* __restrict__ counter;      // pair count mode
 };
 
-// f(r) / (r^2 + eps^2)^(3/2) for 0 < r2.
+// f(r) / (r^2 + eps^2)^(3/2) for 0 <= r < r_c (r = 0 is masked by the caller).
 __device__ __forceinline__ float pair_weight(float r2, float eps2, float inv2rs) {
   const float kP = 0.3275911f;
   const float kA1 = 0.254829592f, kA2 = -0.284496736f, kA3 = 1.421413741f,
@@ -65,8 +68,7 @@ __device__ __forceinline__ float pair_weight(float r2, float eps2, float inv2rs)
   const float kNegLog2e = -1.4426950408889634f;
   float inv = __builtin_amdgcn_rsqf(r2 + eps2);
   float inv3 = inv * inv * inv;
-  float r = __builtin_amdgcn_sqrtf(r2);
-  float u = r * inv2rs;
+  float u = __builtin_amdgcn_sqrtf(r2) * inv2rs;
   float e = __builtin_amdgcn_exp2f(u * u * kNegLog2e);
   float t = __builtin_amdgcn_rcpf(1.0f + kP * u);
   float poly = t * (kA1 + t * (kA2 + t * (kA3 + t * (kA4 + t * kA5))));
@@ -77,8 +79,7 @@ __device__ __forceinline__ float pair_weight(float r2, float eps2, float inv2rs)
 __device__ __forceinline__ double pair_weight(double r2, double eps2, double inv2rs) {
   const double kTwoOverSqrtPi = 1.1283791670955126;
   double inv = rsqrt(r2 + eps2);
-  double r = sqrt(r2);
-  double u = r * inv2rs;
+  double u = sqrt(r2) * inv2rs;
   double f = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
   return f * (inv * inv * inv);
 }
@@ -103,58 +104,45 @@ __device__ __forceinline__ int wave_inclusive(int v) {
   return v;
 }
 
-template <typename T, bool COUNT>
-__global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
+template <typename T>
+struct PairShared {
+  typename Vec<T>::v4 jb[kPairCap + 64];   // staged j (+ far sentinels); reused for the reduction
+  int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
+  T d_sx[64], d_sy[64];
+  int i_lo[16], i_pre[17];
+};
+
+// One work item with U i-slots per lane. UM: every particle has the same mass
+// (mass applied once at the end instead of per pair).
+template <typename T, int U, bool COUNT, bool UM>
+__device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S, int gx0,
+                                          int gy0, int gz0, int ibeg, int ni) {
   using T4 = typename Vec<T>::v4;
-  __shared__ T4 jb[kPairCap + 1];     // + the far sentinel
-  __shared__ int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
-  __shared__ T d_sx[64], d_sy[64];
-  __shared__ int i_lo[16], i_pre[17];
-  __shared__ T red[3][64];
-
   const int lane = threadIdx.x;
-  if ((int)blockIdx.x >= *A.n_items) return;
-  const int2 it = A.items[blockIdx.x];
   const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
-  const int lgd = lg - lgG, md = (1 << lgd) - 1;
-  const int gx0 = (it.x >> (2 * lgd)) << lgG;
-  const int gy0 = ((it.x >> lgd) & md) << lgG;
-  const int gz0 = (it.x & md) << lgG;
   const T h = A.h;
-
-  // i side: the group's G*G z-runs
-  {
-    int cnt = 0;
-    if (lane < GG) {
-      int a = lane >> lgG, b = lane & (G - 1);
-      int c0 = ((((gx0 + a) << lg) | (gy0 + b)) << lg) | gz0;
-      int lo = A.start[c0];
-      i_lo[lane] = lo;
-      cnt = A.start[c0 + G] - lo;
-    }
-    int inc = wave_inclusive(cnt);
-    if (lane < GG) i_pre[lane + 1] = inc;
-    if (lane == 0) i_pre[0] = 0;
-  }
-  __syncthreads();
-  // wave-uniform counts (scalar registers, so the loops below are scalar)
-  const int ntot = __builtin_amdgcn_readfirstlane(i_pre[GG]);
-  const int ibeg = it.y * 64;
-  const int ni = min(64, ntot - ibeg);
-  const int ns = 64 / ni;
-  const int il = lane % ni, st = lane / ni;
+  const int nu = (ni + U - 1) / U;      // slot sets
+  const int ns = 64 / nu;               // streams
+  const int il = lane % nu, st = lane / nu;
   const bool active = st < ns;
-  int run = 0;
-  const int fi = ibeg + il;
-  while (run + 1 < GG && i_pre[run + 1] <= fi) ++run;
-  const int si = i_lo[run] + (fi - i_pre[run]);
-  const T4 pi = A.rec[si];
-  const int czi = A.skey[si] & mask;
-  const T xi = active ? T(run >> lgG) * h + pi.x : kFar;
-  const T yi = active ? T(run & (G - 1)) * h + pi.y : kFar;
-  const T zi = active ? T(czi - gz0) * h + pi.z : kFar;
 
-  T ax = 0, ay = 0, az = 0;
+  T xi[U], yi[U], zi[U], ax[U], ay[U], az[U];
+  int si[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = il + u * nu;            // particle of this slot within the chunk
+    const bool has = active && q < ni;
+    const int fi = ibeg + min(q, ni - 1);
+    int run = 0;
+    while (run + 1 < GG && S.i_pre[run + 1] <= fi) ++run;
+    si[u] = S.i_lo[run] + (fi - S.i_pre[run]);
+    const T4 pi = A.rec[si[u]];
+    const int czi = A.skey[si[u]] & mask;
+    xi[u] = has ? T(run >> lgG) * h + pi.x : T(kFar);
+    yi[u] = has ? T(run & (G - 1)) * h + pi.y : T(kFar);
+    zi[u] = has ? T(czi - gz0) * h + pi.z : T(kFar);
+    ax[u] = ay[u] = az[u] = T(0);
+  }
   int npairs = 0;
 
   for (int rb = 0; rb < A.nrows; rb += 64) {
@@ -188,15 +176,15 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
     int base = inc - tot_l;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      d_lo[3 * lane + k] = lo[k];
-      d_pre[3 * lane + k] = base;
-      d_zs[3 * lane + k] = zs[k];
+      S.d_lo[3 * lane + k] = lo[k];
+      S.d_pre[3 * lane + k] = base;
+      S.d_zs[3 * lane + k] = zs[k];
       base += cnt[k];
     }
-    d_sx[lane] = sx;
-    d_sy[lane] = sy;
+    S.d_sx[lane] = sx;
+    S.d_sy[lane] = sy;
     const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
-    if (lane == 63) d_pre[kDesc] = total;
+    if (lane == 63) S.d_pre[kDesc] = total;
     __syncthreads();
 
     for (int c0 = 0; c0 < total; c0 += kPairCap) {
@@ -208,14 +196,14 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
       {
         const int q0 = kStage * lane;
         int src[kStage], dd[kStage];
-        int d = q0 < cn ? find_desc(d_pre, c0 + q0) : 0;
+        int d = q0 < cn ? find_desc(S.d_pre, c0 + q0) : 0;
 #pragma unroll
         for (int e = 0; e < kStage; ++e) {
           const int f = c0 + q0 + e;
           if (q0 + e < cn)
-            while (d_pre[d + 1] <= f) ++d;
+            while (S.d_pre[d + 1] <= f) ++d;
           dd[e] = d;
-          src[e] = q0 + e < cn ? d_lo[d] + (f - d_pre[d]) : -1;
+          src[e] = q0 + e < cn ? S.d_lo[d] + (f - S.d_pre[d]) : -1;
         }
         T4 pj[kStage];
         int cz[kStage];
@@ -231,42 +219,44 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
           if (src[e] >= 0) {
             const int d = dd[e];
             T4 o;
-            o.x = d_sx[d / 3] + pj[e].x;
-            o.y = d_sy[d / 3] + pj[e].y;
-            o.z = T(cz[e] + d_zs[d]) * h + pj[e].z;
+            o.x = S.d_sx[d / 3] + pj[e].x;
+            o.y = S.d_sy[d / 3] + pj[e].y;
+            o.z = T(cz[e] + S.d_zs[d]) * h + pj[e].z;
             o.w = pj[e].w;
-            jb[q0 + e] = o;
+            S.jb[q0 + e] = o;
           }
         }
       }
-      if (lane == 0) {                 // a far-away sentinel after the last entry
+      {                                // far-away sentinels after the last entry
         T4 far;
-        far.x = far.y = far.z = -kFar;
+        far.x = far.y = far.z = T(-kFar);
         far.w = T(0);
-        jb[cn] = far;
+        S.jb[cn + lane] = far;
       }
       __syncthreads();
-      // lane (il, st) takes staged entries st, st + ns, ...; the trip count is
-      // wave-uniform; reads past the end hit the sentinel, and lanes without
-      // an i sit at +kFar, so both fail the cutoff test
+      // lane (set, stream) takes staged entries st, st + ns, ...; the trip
+      // count is wave-uniform; reads past the end (at most ns - 1) hit the
+      // sentinels, and empty slots sit at +kFar, so both fail the cutoff test
       const int iters = (cn + ns - 1) / ns;
-      for (int t0 = 0; t0 < iters; t0 += kUnroll<T>) {
-        T4 pj[kUnroll<T>];
+      const T4* jp = S.jb + st;
+#pragma unroll 2
+      for (int t = 0; t < iters; ++t) {
+        const T4& pj = jp[t * ns];
+        const T jx = pj.x, jy = pj.y, jz = pj.z;
 #pragma unroll
-        for (int u = 0; u < kUnroll<T>; ++u) pj[u] = jb[min(st + (t0 + u) * ns, cn)];
-#pragma unroll
-        for (int u = 0; u < kUnroll<T>; ++u) {
-          const T dx = xi - pj[u].x, dy = yi - pj[u].y, dz = zi - pj[u].z;
+        for (int u = 0; u < U; ++u) {
+          const T dx = xi[u] - jx, dy = yi[u] - jy, dz = zi[u] - jz;
           const T r2 = dx * dx + dy * dy + dz * dz;
           if (r2 < A.rc2) {
             if (COUNT) {
               npairs += r2 > T(0) ? 1 : 0;
             } else {
-              T w = pj[u].w * pair_weight(r2, A.eps2, A.inv2rs);
+              T w = pair_weight(r2, A.eps2, A.inv2rs);
+              if (!UM) w *= pj.w;
               w = r2 > T(0) ? w : T(0);      // zero separation: no contribution
-              ax += w * dx;
-              ay += w * dy;
-              az += w * dz;
+              ax[u] += w * dx;
+              ay[u] += w * dy;
+              az[u] += w * dz;
             }
           }
         }
@@ -282,25 +272,39 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
     return;
   }
 
-  // add the stream partials of each i
-  red[0][lane] = ax;
-  red[1][lane] = ay;
-  red[2][lane] = az;
+  // add the stream partials of each i: red[c][u][lane], aliasing the j stage
+  __syncthreads();
+  T* red = reinterpret_cast<T*>(S.jb);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    red[(0 * U + u) * 64 + lane] = ax[u];
+    red[(1 * U + u) * 64 + lane] = ay[u];
+    red[(2 * U + u) * 64 + lane] = az[u];
+  }
   __syncthreads();
   if (lane < ni) {
+    const int qs = lane % nu, qu = lane / nu;   // slot set and slot of particle `lane`
     T sx = 0, sy = 0, sz = 0;
+#pragma unroll 2
     for (int k = 0; k < ns; ++k) {
-      sx += red[0][lane + k * ni];
-      sy += red[1][lane + k * ni];
-      sz += red[2][lane + k * ni];
+      sx += red[(0 * U + qu) * 64 + k * nu + qs];
+      sy += red[(1 * U + qu) * 64 + k * nu + qs];
+      sz += red[(2 * U + qu) * 64 + k * nu + qs];
     }
+    const int fi = ibeg + lane;
+    int run = 0;
+    while (run + 1 < GG && S.i_pre[run + 1] <= fi) ++run;
+    const int s = S.i_lo[run] + (fi - S.i_pre[run]);
+    const double m = (double)A.rec[s].w;
     T gx = A.negG * sx, gy = A.negG * sy, gz = A.negG * sz;
+    if (UM) {
+      gx *= T(m); gy *= T(m); gz *= T(m);
+    }
     if (A.acc_pm) {
-      const T4 pm = A.acc_pm[si];
+      const T4 pm = A.acc_pm[s];
       gx += pm.x; gy += pm.y; gz += pm.z;
     }
-    const int64_t i = A.perm[si];
-    const double m = (double)pi.w;
+    const int64_t i = A.perm[s];
     if (A.force_fp32) {
       float* F = (float*)A.force;
       F[i] = (float)(m * (double)gx);
@@ -313,6 +317,44 @@ __global__ void __launch_bounds__(64) k_pairs(PairArgs<T> A) {
       F[2 * A.n + i] = m * (double)gz;
     }
   }
+}
+
+template <typename T, bool COUNT, bool UM>
+__global__ void __launch_bounds__(64)
+k_pairs(PairArgs<T> A) {
+  __shared__ PairShared<T> S;
+  const int lane = threadIdx.x;
+  if ((int)blockIdx.x >= *A.n_items) return;
+  const int2 it = A.items[blockIdx.x];
+  const int lg = A.lg, lgG = A.lgG, G = A.G, GG = G * G;
+  const int lgd = lg - lgG, md = (1 << lgd) - 1;
+  const int gx0 = (it.x >> (2 * lgd)) << lgG;
+  const int gy0 = ((it.x >> lgd) & md) << lgG;
+  const int gz0 = (it.x & md) << lgG;
+
+  // i side: the group's G*G z-runs
+  {
+    int cnt = 0;
+    if (lane < GG) {
+      int a = lane >> lgG, b = lane & (G - 1);
+      int c0 = ((((gx0 + a) << lg) | (gy0 + b)) << lg) | gz0;
+      int lo = A.start[c0];
+      S.i_lo[lane] = lo;
+      cnt = A.start[c0 + G] - lo;
+    }
+    int inc = wave_inclusive(cnt);
+    if (lane < GG) S.i_pre[lane + 1] = inc;
+    if (lane == 0) S.i_pre[0] = 0;
+  }
+  __syncthreads();
+  // wave-uniform counts (scalar registers, so the loops are scalar)
+  const int ntot = __builtin_amdgcn_readfirstlane(S.i_pre[GG]);
+  const int ibeg = it.y * 64;
+  const int ni = min(64, ntot - ibeg);
+  if (ni == 1)
+    pair_item<T, 1, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+  else
+    pair_item<T, sizeof(T) == 4 ? 4 : 2, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
 }
 
 template <typename T>
@@ -343,12 +385,16 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32) {
+hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32,
+                        bool uniform_mass) {
   PairArgs<T> A = make_args<T>(P, n);
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
   A.force = force_out;
   A.force_fp32 = force_fp32;
-  k_pairs<T, false><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
+  if (uniform_mass)
+    k_pairs<T, false, true><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
+  else
+    k_pairs<T, false, false><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -358,12 +404,12 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
   A.counter = (unsigned long long*)count_out;
   hipError_t e = launch_fill_i32((int32_t*)count_out, 2, 0, P->stream);
   if (e != hipSuccess) return e;
-  k_pairs<T, true><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
+  k_pairs<T, true, true><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
   return hipGetLastError();
 }
 
-template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int);
-template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int);
+template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int, bool);
+template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, bool);
 template hipError_t launch_pair_count<float>(p3m_plan*, int64_t, int64_t*);
 template hipError_t launch_pair_count<double>(p3m_plan*, int64_t, int64_t*);
 
