@@ -30,6 +30,34 @@ int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out,
  * 8 particles per group, never larger than grid_n / 2. */
 int32_t p3m_group_edge(int64_t n, int32_t grid_n);
 
+/* Background cosmology for comoving kick and drift coefficients (CONCEPT
+ * User's Guide, Ch. 5: H0, Omega_m, Omega_Lambda, a_begin, and a time step
+ * given as a fraction of the age of the universe; Ch. 6: comoving positions
+ * and momenta). H(a) = H0 sqrt(Omega_m a^-3 + Omega_k a^-2 + Omega_Lambda)
+ * with Omega_k = 1 - Omega_m - Omega_Lambda; H0 in inverse time units of the
+ * simulation. Errors: P3M_EINVAL for a null pointer, H0 <= 0, Omega_m <= 0,
+ * non-finite values or a <= 0; P3M_ERANGE if H^2 <= 0 somewhere on the
+ * range (a turnaround). */
+typedef struct p3m_cosmology {
+  double H0;
+  double Omega_m;
+  double Omega_L;
+} p3m_cosmology;
+
+/* Age t(a) = int_0^a da' / (a' H(a')). */
+int p3m_cosmo_age(const p3m_cosmology* c, double a, double* t_out);
+
+/* Inverse of the age: the scale factor a with t(a) = t (t > 0). */
+int p3m_cosmo_scale_factor(const p3m_cosmology* c, double t, double* a_out);
+
+/* Leapfrog coefficients between scale factors a0 <= a1, for canonical
+ * momenta p = a^2 m dx/dt and a force F = -m grad(phi) computed from the
+ * comoving density: c_kick = int dt / a (use p += c_kick F) and
+ * c_drift = int dt / a^2 (use x += c_drift p / m), both integrated over
+ * a in [a0, a1] with dt = da / (a H(a)). */
+int p3m_cosmo_kick_drift(const p3m_cosmology* c, double a0, double a1, double* c_kick,
+                         double* c_drift);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,11 @@ class P3MParams(ctypes.Structure):
     ]
 
 
+class P3MCosmology(ctypes.Structure):
+    _fields_ = [("H0", ctypes.c_double), ("Omega_m", ctypes.c_double),
+                ("Omega_L", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
@@ -61,6 +66,12 @@ def _load():
         "p3m_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "p3m_stencil_rows": (i32, [i32, dbl, ctypes.POINTER(i32), i32]),
         "p3m_group_edge": (i32, [i64, i32]),
+        "p3m_cosmo_age": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
+                                         ctypes.POINTER(dbl)]),
+        "p3m_cosmo_scale_factor": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
+                                                  ctypes.POINTER(dbl)]),
+        "p3m_cosmo_kick_drift": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl, dbl,
+                                                ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -122,6 +133,51 @@ def stencil_rows(g: int, radius_cells: float):
 
 def group_edge(n: int, grid_n: int) -> int:
     return int(_lib.p3m_group_edge(n, grid_n))
+
+
+@dataclass(frozen=True)
+class Cosmology:
+    """Background (guide Ch. 5: H0, Omega_m, Omega_Lambda); H0 in the inverse
+    time unit of the simulation."""
+    H0: float
+    Omega_m: float
+    Omega_L: float = 0.0
+
+    def _c(self):
+        return P3MCosmology(float(self.H0), float(self.Omega_m), float(self.Omega_L))
+
+    def age(self, a: float) -> float:
+        out = ctypes.c_double()
+        _check(_lib.p3m_cosmo_age(ctypes.byref(self._c()), float(a), ctypes.byref(out)),
+               "p3m_cosmo_age")
+        return out.value
+
+    def scale_factor(self, t: float) -> float:
+        out = ctypes.c_double()
+        _check(_lib.p3m_cosmo_scale_factor(ctypes.byref(self._c()), float(t),
+                                           ctypes.byref(out)), "p3m_cosmo_scale_factor")
+        return out.value
+
+    def kick_drift(self, a0: float, a1: float):
+        """(c_kick, c_drift) = (int dt/a, int dt/a^2) from a0 to a1."""
+        ck, cd = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.p3m_cosmo_kick_drift(ctypes.byref(self._c()), float(a0), float(a1),
+                                         ctypes.byref(ck), ctypes.byref(cd)),
+               "p3m_cosmo_kick_drift")
+        return ck.value, cd.value
+
+    def kdk_step(self, a: float, dt_factor: float):
+        """One kick-drift-kick step of length dt_factor times the age at a
+        (guide Ch. 5, Delta t_factor): returns (a_next, c_kick_first, c_drift,
+        c_kick_second), the kicks covering the first and second half in time."""
+        t0 = self.age(a)
+        dt = dt_factor * t0
+        a_half = self.scale_factor(t0 + 0.5 * dt)
+        a_next = self.scale_factor(t0 + dt)
+        k1, _ = self.kick_drift(a, a_half)
+        k2, _ = self.kick_drift(a_half, a_next)
+        _, d = self.kick_drift(a, a_next)
+        return a_next, k1, d, k2
 
 
 @dataclass

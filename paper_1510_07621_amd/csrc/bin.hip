@@ -162,7 +162,7 @@ __global__ void k_group_chunks(const int32_t* __restrict__ start, int ng, int lg
       int c0 = ((((gx * G + a) << lg) | (gy * G + b)) << lg) | (gz * G);
       cnt += start[c0 + G] - start[c0];
     }
-  gchunk[g] = (cnt + 63) >> 6;
+  gchunk[g] = (cnt + kChunk - 1) / kChunk;
 }
 
 __global__ void k_emit_items(const int32_t* __restrict__ gchunk,

@@ -200,7 +200,7 @@ int32_t p3m_group_edge(int64_t n, int32_t grid_n) {
   double best_err = 1e300;
   for (int g = 1; g <= 4 && g <= grid_n / 2; g *= 2) {
     double mean = (double)g * g * g / cells_per_particle;
-    double err = std::fabs(std::log(mean / 8.0));
+    double err = std::fabs(std::log(mean / kGroupTarget));
     if (err < best_err) {
       best_err = err;
       best = g;
@@ -259,7 +259,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   P->ngd = q.grid_n / P->G;
   P->ngroup = (int64_t)P->ngd * P->ngd * P->ngd;
   P->nrows = stencil_rows(P->G, r_c / h, nullptr, 0);
-  P->max_items = P->ngroup + (n_max + 63) / 64;
+  P->max_items = P->ngroup + (n_max + kChunk - 1) / kChunk;
   const int64_t nspec = (int64_t)q.grid_n * q.grid_n * (q.grid_n / 2 + 1);
   const size_t real = q.precision == P3M_FP32 ? sizeof(float) : sizeof(double);
   const int64_t nn = n_max > 0 ? n_max : 1;

@@ -23,6 +23,9 @@ template <> struct Vec<double> {
 
 constexpr int kPairCap = 256;     // j-particles staged in LDS per pass of the pair loop
 constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
+constexpr int kChunk = 128;       // i-particles per pair-loop work item (one wavefront)
+constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
+constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
 
 // One particle in cell order: offsets from its cell's lower corner and mass.
 // (x, y, z, m) as float4 (FP32 path) or double4 (FP64 path).

@@ -272,26 +272,27 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
     return;
   }
 
-  // add the stream partials of each i: red[c][u][lane], aliasing the j stage
-  __syncthreads();
+  // add the stream partials of each i, one slot at a time: red[c][lane]
+  // (aliasing the j stage); particle u * nu + q is the sum over streams k of
+  // lane k * nu + q's slot u
   T* red = reinterpret_cast<T*>(S.jb);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    red[(0 * U + u) * 64 + lane] = ax[u];
-    red[(1 * U + u) * 64 + lane] = ay[u];
-    red[(2 * U + u) * 64 + lane] = az[u];
-  }
-  __syncthreads();
-  if (lane < ni) {
-    const int qs = lane % nu, qu = lane / nu;   // slot set and slot of particle `lane`
+    __syncthreads();
+    red[0 * 64 + lane] = ax[u];
+    red[1 * 64 + lane] = ay[u];
+    red[2 * 64 + lane] = az[u];
+    __syncthreads();
+    const int q = u * nu + lane;
+    if (lane >= nu || q >= ni) continue;
     T sx = 0, sy = 0, sz = 0;
 #pragma unroll 2
     for (int k = 0; k < ns; ++k) {
-      sx += red[(0 * U + qu) * 64 + k * nu + qs];
-      sy += red[(1 * U + qu) * 64 + k * nu + qs];
-      sz += red[(2 * U + qu) * 64 + k * nu + qs];
+      sx += red[0 * 64 + k * nu + lane];
+      sy += red[1 * 64 + k * nu + lane];
+      sz += red[2 * 64 + k * nu + lane];
     }
-    const int fi = ibeg + lane;
+    const int fi = ibeg + q;
     int run = 0;
     while (run + 1 < GG && S.i_pre[run + 1] <= fi) ++run;
     const int s = S.i_lo[run] + (fi - S.i_pre[run]);
@@ -324,8 +325,12 @@ __global__ void __launch_bounds__(64)
 k_pairs(PairArgs<T> A) {
   __shared__ PairShared<T> S;
   const int lane = threadIdx.x;
-  if ((int)blockIdx.x >= *A.n_items) return;
-  const int2 it = A.items[blockIdx.x];
+  // Items in group order, dealt round-robin over the XCDs by the hardware:
+  // the eight XCDs then work on neighbouring groups at the same time, which
+  // measured faster than giving each XCD its own slab of the box.
+  const int item = (int)blockIdx.x;
+  if (item >= *A.n_items) return;
+  const int2 it = A.items[item];
   const int lg = A.lg, lgG = A.lgG, G = A.G, GG = G * G;
   const int lgd = lg - lgG, md = (1 << lgd) - 1;
   const int gx0 = (it.x >> (2 * lgd)) << lgG;
@@ -349,12 +354,22 @@ k_pairs(PairArgs<T> A) {
   __syncthreads();
   // wave-uniform counts (scalar registers, so the loops are scalar)
   const int ntot = __builtin_amdgcn_readfirstlane(S.i_pre[GG]);
-  const int ibeg = it.y * 64;
-  const int ni = min(64, ntot - ibeg);
+  const int ibeg = it.y * kChunk;
+  const int ni = min(kChunk, ntot - ibeg);
+  // i-slots per lane: enough that ceil(ni / U) slot sets fit in the wave
   if (ni == 1)
     pair_item<T, 1, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+  else if (sizeof(T) == 8)
+    pair_item<T, 2, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+  else if (ni <= 64)
+    pair_item<T, 4, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
   else
-    pair_item<T, sizeof(T) == 4 ? 4 : 2, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 8, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+}
+
+// Grid of the pair kernel: the item bound rounded up to a multiple of kXcds.
+unsigned pair_grid(const p3m_plan* P) {
+  return (unsigned)((P->max_items + kXcds - 1) / kXcds * kXcds);
 }
 
 template <typename T>
@@ -391,10 +406,11 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
   A.force = force_out;
   A.force_fp32 = force_fp32;
+  const unsigned grid = pair_grid(P);
   if (uniform_mass)
-    k_pairs<T, false, true><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
+    k_pairs<T, false, true><<<grid, 64, 0, P->stream>>>(A);
   else
-    k_pairs<T, false, false><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
+    k_pairs<T, false, false><<<grid, 64, 0, P->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -404,7 +420,7 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
   A.counter = (unsigned long long*)count_out;
   hipError_t e = launch_fill_i32((int32_t*)count_out, 2, 0, P->stream);
   if (e != hipSuccess) return e;
-  k_pairs<T, true, true><<<(unsigned)P->max_items, 64, 0, P->stream>>>(A);
+  k_pairs<T, true, true><<<pair_grid(P), 64, 0, P->stream>>>(A);
   return hipGetLastError();
 }
 

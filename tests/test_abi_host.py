@@ -147,8 +147,9 @@ def test_stencil_contains_every_partner_cell_of_random_pairs(b):
 
 
 def test_group_edge(b):
-    assert b.group_edge(128 ** 3, 128) == 2        # one particle per cell -> 8 per group
-    assert b.group_edge(16 ** 3, 128) == 4         # sparse
-    assert b.group_edge(8 * 64 ** 3, 64) == 1      # dense
+    assert b.group_edge(128 ** 3, 128) == 4        # one particle per cell -> 64 per group
+    assert b.group_edge(16 ** 3, 128) == 4         # sparse: largest group
+    assert b.group_edge(8 * 64 ** 3, 64) == 2      # eight per cell -> 64 per group
+    assert b.group_edge(64 * 32 ** 3, 32) == 1     # dense
     assert b.group_edge(0, 64) == 1
     assert b.group_edge(10 ** 9, 16) == 1
