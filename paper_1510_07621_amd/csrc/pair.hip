@@ -84,16 +84,6 @@ __device__ __forceinline__ double pair_weight(double r2, double eps2, double inv
   return f * (inv * inv * inv);
 }
 
-// Largest d with pre[d] <= f (pre non-decreasing, pre[0] = 0 <= f < pre[kDesc]).
-__device__ __forceinline__ int find_desc(const int* __restrict__ pre, int f) {
-  int lo = 0, hi = kDesc;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (pre[mid] <= f) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int wave_inclusive(int v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -108,9 +98,51 @@ template <typename T>
 struct PairShared {
   typename Vec<T>::v4 jb[kPairCap + 64];   // staged j (+ far sentinels); reused for the reduction
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
+  int owner[kPairCap];                     // run of each staged entry of a chunk
   T d_sx[64], d_sy[64];
   int i_lo[16], i_pre[17];
 };
+
+// One stencil row (per lane) resolved into at most three contiguous sorted
+// runs (the z-run split where it crosses the periodic box face): first slot,
+// count and the unwrapped z-cell shift of each run relative to the group.
+template <typename T>
+struct RowRuns {
+  int cnt[3], lo[3], zs[3];
+  T sx, sy;                                 // x, y shift of the row's column
+};
+
+template <typename T>
+__device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, int rb, int lane,
+                                                   int gx0, int gy0, int gz0) {
+  RowRuns<T> R;
+  const int lg = A.lg, ng = A.ng, mask = ng - 1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) R.cnt[k] = R.lo[k] = R.zs[k] = 0;
+  R.sx = R.sy = T(0);
+  if (rb + lane < A.nrows) {
+    const int4 row = A.rows[rb + lane];
+    const int jx = (gx0 + row.x) & mask, jy = (gy0 + row.y) & mask;
+    R.sx = T(row.x) * A.h;
+    R.sy = T(row.y) * A.h;
+    const int zhi = gz0 + row.w;
+    int z = gz0 + row.z;
+    const int cbase = ((jx << lg) | jy) << lg;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (z <= zhi) {
+        int zw = z & mask;
+        int len = min(zhi - z + 1, ng - zw);
+        int l0 = A.start[cbase + zw];
+        R.lo[k] = l0;
+        R.cnt[k] = A.start[cbase + zw + len] - l0;
+        R.zs[k] = (z - zw) - gz0;
+        z += len;
+      }
+    }
+  }
+  return R;
+}
 
 // One work item with U i-slots per lane. UM: every particle has the same mass
 // (mass applied once at the end instead of per pair).
@@ -145,65 +177,77 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
   }
   int npairs = 0;
 
+  // Stencil rows are resolved 64 at a time (one per lane); the next batch's
+  // start[] lookups are issued before the current batch's pair loop so their
+  // latency hides behind it.
+  RowRuns<T> nxt = resolve_rows<T>(A, 0, lane, gx0, gy0, gz0);
   for (int rb = 0; rb < A.nrows; rb += 64) {
-    // resolve one stencil row per lane into up to three sorted runs
-    int cnt[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, zs[3] = {0, 0, 0};
-    T sx = 0, sy = 0;
-    if (rb + lane < A.nrows) {
-      const int4 row = A.rows[rb + lane];
-      const int jx = (gx0 + row.x) & mask, jy = (gy0 + row.y) & mask;
-      sx = T(row.x) * h;
-      sy = T(row.y) * h;
-      const int zhi = gz0 + row.w;
-      int z = gz0 + row.z;
-      const int cbase = ((jx << lg) | jy) << lg;
+    const RowRuns<T> cur = nxt;
+    __syncthreads();       // previous batch is done with the descriptors and jb
+    const int tot_l = cur.cnt[0] + cur.cnt[1] + cur.cnt[2];
+    const int inc = wave_inclusive(tot_l);
+    int pre[3];
+    {
+      int base = inc - tot_l;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        if (z <= zhi) {
-          int zw = z & mask;
-          int len = min(zhi - z + 1, ng - zw);
-          int l0 = A.start[cbase + zw];
-          lo[k] = l0;
-          cnt[k] = A.start[cbase + zw + len] - l0;
-          zs[k] = (z - zw) - gz0;
-          z += len;
-        }
+        pre[k] = base;
+        S.d_lo[3 * lane + k] = cur.lo[k];
+        S.d_pre[3 * lane + k] = base;
+        S.d_zs[3 * lane + k] = cur.zs[k];
+        base += cur.cnt[k];
       }
     }
-    __syncthreads();       // previous batch is done with the descriptors and jb
-    const int tot_l = cnt[0] + cnt[1] + cnt[2];
-    const int inc = wave_inclusive(tot_l);
-    int base = inc - tot_l;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      S.d_lo[3 * lane + k] = lo[k];
-      S.d_pre[3 * lane + k] = base;
-      S.d_zs[3 * lane + k] = zs[k];
-      base += cnt[k];
-    }
-    S.d_sx[lane] = sx;
-    S.d_sy[lane] = sy;
+    S.d_sx[lane] = cur.sx;
+    S.d_sy[lane] = cur.sy;
     const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
     if (lane == 63) S.d_pre[kDesc] = total;
-    __syncthreads();
+    if (total == 0 && rb + 64 < A.nrows)          // empty batch: nothing to overlap with
+      nxt = resolve_rows<T>(A, rb + 64, lane, gx0, gy0, gz0);
 
     for (int c0 = 0; c0 < total; c0 += kPairCap) {
       const int cn = min(kPairCap, total - c0);
-      if (c0 > 0) __syncthreads();
-      // stage entries [kStage*lane, kStage*lane + kStage) of this chunk: one
-      // search for the first, a short forward walk for the rest, then all
+      __syncthreads();     // descriptors visible; previous chunk done with jb
+      // owner[q] = run of chunk entry q: each run marks its first entry in the
+      // chunk, then a prefix maximum over the chunk fills the rest
+      const int q0 = kStage * lane;
+#pragma unroll
+      for (int e = 0; e < kStage; ++e) S.owner[q0 + e] = -1;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int s = pre[k] - c0;
+        if (cur.cnt[k] > 0 && s + cur.cnt[k] > 0 && s < cn) S.owner[max(s, 0)] = 3 * lane + k;
+      }
+      __syncthreads();
+      int dd[kStage];
+      {
+        int run = -1;
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) {
+          run = max(run, S.owner[q0 + e]);
+          dd[e] = run;
+        }
+        // exclusive prefix maximum of the lanes' last values
+        int carry = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          int t = __shfl_up(carry, o, 64);
+          if (lane >= o) carry = max(carry, t);
+        }
+        int before = __shfl_up(carry, 1, 64);
+        if (lane == 0) before = -1;
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) dd[e] = max(dd[e], before);
+      }
+      // stage entries [kStage*lane, kStage*lane + kStage) of this chunk, all
       // loads in flight together
       {
-        const int q0 = kStage * lane;
-        int src[kStage], dd[kStage];
-        int d = q0 < cn ? find_desc(S.d_pre, c0 + q0) : 0;
+        int src[kStage];
 #pragma unroll
         for (int e = 0; e < kStage; ++e) {
           const int f = c0 + q0 + e;
-          if (q0 + e < cn)
-            while (S.d_pre[d + 1] <= f) ++d;
-          dd[e] = d;
-          src[e] = q0 + e < cn ? S.d_lo[d] + (f - S.d_pre[d]) : -1;
+          src[e] = q0 + e < cn ? S.d_lo[dd[e]] + (f - S.d_pre[dd[e]]) : -1;
         }
         T4 pj[kStage];
         int cz[kStage];
@@ -233,6 +277,8 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
         far.w = T(0);
         S.jb[cn + lane] = far;
       }
+      if (c0 + kPairCap >= total && rb + 64 < A.nrows)
+        nxt = resolve_rows<T>(A, rb + 64, lane, gx0, gy0, gz0);   // in flight during the loop
       __syncthreads();
       // lane (set, stream) takes staged entries st, st + ns, ...; the trip
       // count is wave-uniform; reads past the end (at most ns - 1) hit the
