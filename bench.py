@@ -46,7 +46,30 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 step timing")
     ap.add_argument("--cpu-sample", type=int, default=20000,
                     help="particles whose short-range force the CPU oracle evaluates")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device (a plain copy "
+                         "of known size, to scale memory counters in a profiled run)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_zeldovich128_traffic.json")
+PAIR_SOURCE = os.path.join(ROOT, "paper_1510_07621_amd", "csrc", "pair.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_pairs launch from the committed counter summary, or
+    None when the pair kernel's source changed after the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(PAIR_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("pair_source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def run_steps(binding, plan, x, p, F, m, dt, box, steps):
@@ -174,7 +197,7 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "flop_per_pair": FLOP_PER_PAIR,
             "avg_launch_ms": pp_ms,
         },
@@ -197,6 +220,14 @@ def main():
         out["cpu_baseline"] = base
         out["force_err_vs_oracle"] = {k: {"rms": v["rms"], "max": v["max"]}
                                       for k, v in errs.items()}
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
     print(json.dumps(out))
 
 
