@@ -25,6 +25,16 @@ extern "C" {
 int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out,
                          int32_t cap);
 
+/* Table of the split factor f(u) = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
+ * u = r / (2 r_s), that the FP32 pair sum evaluates: u in [0, cutoff_rs / 2]
+ * is cut into B equal bins, and bin k holds the cubic
+ * c0 + c1 t + c2 t^2 + c3 t^3 (t in [0, 1] across the bin) through f at the
+ * four Chebyshev points of the bin; entry B is the constant f at the cutoff.
+ * Layout: out[c * (B + 1) + k] for c = 0..3, k = 0..B. Returns B and writes
+ * the 4 (B + 1) floats when cap >= 4 (B + 1) (out may be NULL with cap == 0).
+ * P3M_EINVAL (-1) for cutoff_rs <= 0 or non-finite, or cap > 0 with NULL out. */
+int32_t p3m_split_table(double cutoff_rs, float* out, int32_t cap);
+
 /* Edge, in cells, of the i-groups the pair sum uses for n particles on a
  * grid of grid_n^3 cells: the power of two (1, 2 or 4) closest to a mean of
  * 8 particles per group, never larger than grid_n / 2. */

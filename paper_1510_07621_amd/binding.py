@@ -66,6 +66,7 @@ def _load():
         "p3m_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "p3m_stencil_rows": (i32, [i32, dbl, ctypes.POINTER(i32), i32]),
         "p3m_group_edge": (i32, [i64, i32]),
+        "p3m_split_table": (i32, [dbl, ctypes.POINTER(ctypes.c_float), i32]),
         "p3m_cosmo_age": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
                                          ctypes.POINTER(dbl)]),
         "p3m_cosmo_scale_factor": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
@@ -133,6 +134,17 @@ def stencil_rows(g: int, radius_cells: float):
 
 def group_edge(n: int, grid_n: int) -> int:
     return int(_lib.p3m_group_edge(n, grid_n))
+
+
+def split_table(cutoff_rs: float):
+    """FP32 split-factor table of the pair sum: a (4, B + 1) float32 array of
+    cubic coefficients c0..c3 per bin of u in [0, cutoff_rs / 2]."""
+    import numpy as np
+    b = _lib.p3m_split_table(cutoff_rs, None, 0)
+    _check(min(b, 0), "p3m_split_table")
+    buf = (ctypes.c_float * (4 * (b + 1)))()
+    _lib.p3m_split_table(cutoff_rs, buf, 4 * (b + 1))
+    return np.frombuffer(buf, dtype=np.float32).reshape(4, b + 1).copy()
 
 
 @dataclass(frozen=True)

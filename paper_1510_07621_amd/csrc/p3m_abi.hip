@@ -42,7 +42,7 @@ void free_workspace(p3m_plan* P) {
   Workspace& W = P->ws;
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
-                  W.spec, W.twiddle, W.gtab,  W.counter};
+                  W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -150,6 +150,42 @@ int force_entry(p3m_plan* P, int64_t n, const double* pos, const double* mass, d
 
 namespace p3m {
 
+// Split factor f(u) = erfc(u) + (2u/sqrt(pi)) exp(-u^2), u = r / (2 r_s).
+static double split_f(double u) {
+  return std::erfc(u) + 1.1283791670955126 * u * std::exp(-u * u);
+}
+
+void split_table(double u_c, int bins, float* out) {
+  // Bin k covers u = (k + t) u_c / bins, t in [0, 1]: the cubic through f at
+  // the four Chebyshev points of [0, 1] (4x4 Vandermonde solve). Entry `bins`
+  // is the constant f(u_c), for arguments rounded up onto the cutoff.
+  const double kPi = 3.14159265358979323846;
+  const int stride = bins + 1;
+  for (int k = 0; k < bins; ++k) {
+    double V[4][5];
+    for (int j = 0; j < 4; ++j) {
+      double t = 0.5 - 0.5 * std::cos((2 * j + 1) * kPi / 8.0);
+      double p = 1.0;
+      for (int l = 0; l < 4; ++l, p *= t) V[j][l] = p;
+      V[j][4] = split_f((k + t) * u_c / bins);
+    }
+    for (int c = 0; c < 4; ++c) {           // Gauss-Jordan, partial pivoting
+      int piv = c;
+      for (int r = c + 1; r < 4; ++r)
+        if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
+      for (int l = 0; l < 5; ++l) std::swap(V[c][l], V[piv][l]);
+      for (int r = 0; r < 4; ++r) {
+        if (r == c) continue;
+        double m = V[r][c] / V[c][c];
+        for (int l = c; l < 5; ++l) V[r][l] -= m * V[c][l];
+      }
+    }
+    for (int l = 0; l < 4; ++l) out[l * stride + k] = (float)(V[l][4] / V[l][l]);
+  }
+  out[0 * stride + bins] = (float)split_f(u_c);
+  out[1 * stride + bins] = out[2 * stride + bins] = out[3 * stride + bins] = 0.0f;
+}
+
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
   if (g < 1 || !(radius_cells > 0) || !std::isfinite(radius_cells)) return P3M_EINVAL;
   // A cell can hold a partner closer than r_c iff its gap to the group box is
@@ -191,6 +227,13 @@ extern "C" {
 int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out, int32_t cap) {
   if (cap < 0 || (cap > 0 && !rows_out)) return P3M_EINVAL;
   return p3m::stencil_rows(g, radius_cells, rows_out, cap);
+}
+
+int32_t p3m_split_table(double cutoff_rs, float* out, int32_t cap) {
+  if (!(cutoff_rs > 0) || !std::isfinite(cutoff_rs) || cap < 0 || (cap > 0 && !out))
+    return P3M_EINVAL;
+  if (cap >= 4 * (kSplitBins + 1)) p3m::split_table(0.5 * cutoff_rs, kSplitBins, out);
+  return kSplitBins;
 }
 
 int32_t p3m_group_edge(int64_t n, int32_t grid_n) {
@@ -285,6 +328,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   W.twiddle = dev_alloc<unsigned char>((q.grid_n / 2) * 2 * real, err);
   W.gtab = dev_alloc<unsigned char>(2 * q.grid_n * real, err);
   W.counter = dev_alloc<unsigned long long>(1, err);
+  W.split_tab = dev_alloc<float>(4 * (kSplitBins + 1), err);
   if (err == hipSuccess) {
     int32_t* rows = new (std::nothrow) int32_t[4 * (size_t)P->nrows];
     if (!rows) {
@@ -295,6 +339,11 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
     stencil_rows(P->G, r_c / h, rows, P->nrows);
     err = hipMemcpy(W.rows, rows, sizeof(int4) * P->nrows, hipMemcpyHostToDevice);
     delete[] rows;
+  }
+  if (err == hipSuccess) {
+    float tab[4 * (kSplitBins + 1)];
+    split_table(0.5 * q.cutoff_rs, kSplitBins, tab);     // u_c = r_c / (2 r_s)
+    err = hipMemcpy(W.split_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
   }
   if (err == hipSuccess)
     err = q.precision == P3M_FP32 ? launch_tables<float>(P) : launch_tables<double>(P);

@@ -25,6 +25,7 @@ constexpr int kPairCap = 256;     // j-particles staged in LDS per pass of the p
 constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
 constexpr int kChunk = 128;       // i-particles per pair-loop work item (one wavefront)
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
+constexpr int kSplitBins = 64;    // cubic pieces of the FP32 split-factor table
 constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
 
 // One particle in cell order: offsets from its cell's lower corner and mass.
@@ -49,6 +50,7 @@ struct Workspace {
   void* twiddle = nullptr;      // [ng/2]    exp(-2 pi i k / ng) (T2)
   void* gtab = nullptr;         // [2*ng]    Green's function factor tables (T)
   unsigned long long* counter = nullptr;  // [1] pair-count scratch
+  float* split_tab = nullptr;   // [4][kSplitBins + 1] cubic pieces of f(r) on [0, r_c)
 };
 
 }  // namespace p3m
@@ -110,5 +112,7 @@ hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double*
 
 // Host geometry helpers.
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap);
+// Split-factor table: out[c * (bins + 1) + k] is coefficient c of bin k.
+void split_table(double u_c, int bins, float* out);
 
 }  // namespace p3m

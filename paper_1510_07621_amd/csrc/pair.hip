@@ -25,10 +25,11 @@
 // rebuilt from cell-relative offsets and small integer cell differences, so
 // the FP32 path never subtracts two large coordinates.
 //
-// Arithmetic. FP32: rsq(r^2 + eps^2), sqrt(r^2), exp(-u^2), and erfc(u) from
-// the Abramowitz & Stegun 7.1.26 rational form t P(t) exp(-u^2),
-// t = 1/(1 + p u) (absolute error <= 1.5e-7), sharing the exponential.
-// FP64: the device library's erfc, exp, sqrt and rsqrt.
+// Arithmetic. FP32: rsq(r^2 + eps^2), sqrt(r^2), and f from a table of 64
+// cubic pieces over [0, r_c) held in LDS (fitted in FP64 by the plan at the
+// Chebyshev points of each piece; error well below FP32 rounding), so a pair
+// costs two transcendentals instead of four. FP64: the device library's erfc,
+// exp, sqrt and rsqrt.
 #include "p3m_internal.h"
 
 namespace p3m {
@@ -51,6 +52,8 @@ struct PairArgs {
   int nrows;
   int ng, lg, G, lgG;
   T h, rc2, eps2, inv2rs, negG;
+  const float* __restrict__ split_tab;  // FP32 split-factor table [4][kSplitBins + 1]
+  float xscale;                         // kSplitBins / r_c
   const typename Vec<T>::v4* __restrict__ acc_pm;  // sorted PM acceleration or null
   const int32_t* __restrict__ perm;
   int64_t n;
@@ -59,27 +62,31 @@ struct PairArgs {
   unsigned long long* __restrict__ counter;      // pair count mode
 };
 
+// The FP32 split-factor table in LDS: four coefficient arrays, so that the
+// random per-lane bin lookups spread over the banks.
+constexpr int kTabStride = kSplitBins + 1;
+struct SplitTable {
+  float c[4][kTabStride];
+};
+
 // f(r) / (r^2 + eps^2)^(3/2) for 0 <= r < r_c (r = 0 is masked by the caller).
-__device__ __forceinline__ float pair_weight(float r2, float eps2, float inv2rs) {
-  const float kP = 0.3275911f;
-  const float kA1 = 0.254829592f, kA2 = -0.284496736f, kA3 = 1.421413741f,
-              kA4 = -1.453152027f, kA5 = 1.061405429f;
-  const float kTwoOverSqrtPi = 1.1283791670955126f;
-  const float kNegLog2e = -1.4426950408889634f;
-  float inv = __builtin_amdgcn_rsqf(r2 + eps2);
+// FP32: f from the plan's piecewise-cubic table over x = r * kSplitBins / r_c.
+__device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
+                                             const SplitTable& tab) {
+  float inv = __builtin_amdgcn_rsqf(r2 + A.eps2);
   float inv3 = inv * inv * inv;
-  float u = __builtin_amdgcn_sqrtf(r2) * inv2rs;
-  float e = __builtin_amdgcn_exp2f(u * u * kNegLog2e);
-  float t = __builtin_amdgcn_rcpf(1.0f + kP * u);
-  float poly = t * (kA1 + t * (kA2 + t * (kA3 + t * (kA4 + t * kA5))));
-  float f = e * (poly + kTwoOverSqrtPi * u);
+  float x = __builtin_amdgcn_sqrtf(r2) * A.xscale;
+  int k = (int)x;                       // < kSplitBins + 1 since r < r_c
+  float t = x - (float)k;
+  float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
   return f * inv3;
 }
 
-__device__ __forceinline__ double pair_weight(double r2, double eps2, double inv2rs) {
+__device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>& A,
+                                              const SplitTable&) {
   const double kTwoOverSqrtPi = 1.1283791670955126;
-  double inv = rsqrt(r2 + eps2);
-  double u = sqrt(r2) * inv2rs;
+  double inv = rsqrt(r2 + A.eps2);
+  double u = sqrt(r2) * A.inv2rs;
   double f = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
   return f * (inv * inv * inv);
 }
@@ -101,6 +108,7 @@ struct PairShared {
   int owner[kPairCap];                     // run of each staged entry of a chunk
   T d_sx[64], d_sy[64];
   int i_lo[16], i_pre[17];
+  SplitTable tab;                          // FP32 path only
 };
 
 // One stencil row (per lane) resolved into at most three contiguous sorted
@@ -297,7 +305,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
             if (COUNT) {
               npairs += r2 > T(0) ? 1 : 0;
             } else {
-              T w = pair_weight(r2, A.eps2, A.inv2rs);
+              T w = pair_weight(r2, A, S.tab);
               if (!UM) w *= pj.w;
               w = r2 > T(0) ? w : T(0);      // zero separation: no contribution
               ax[u] += w * dx;
@@ -383,6 +391,10 @@ k_pairs(PairArgs<T> A) {
   const int gy0 = ((it.x >> lgd) & md) << lgG;
   const int gz0 = (it.x & md) << lgG;
 
+  if (sizeof(T) == 4 && !COUNT) {      // split-factor table into LDS
+    float* tab = &S.tab.c[0][0];
+    for (int e = lane; e < 4 * kTabStride; e += 64) tab[e] = A.split_tab[e];
+  }
   // i side: the group's G*G z-runs
   {
     int cnt = 0;
@@ -438,6 +450,8 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.eps2 = (T)(P->eps * P->eps);
   A.inv2rs = (T)(1.0 / (2.0 * P->r_s));
   A.negG = (T)(-P->prm.G);
+  A.split_tab = W.split_tab;
+  A.xscale = (float)(kSplitBins / P->r_c);
   A.perm = W.perm;
   A.n = n;
   return A;

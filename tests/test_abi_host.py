@@ -153,3 +153,37 @@ def test_group_edge(b):
     assert b.group_edge(64 * 32 ** 3, 32) == 1     # dense
     assert b.group_edge(0, 64) == 1
     assert b.group_edge(10 ** 9, 16) == 1
+
+
+@pytest.mark.parametrize("cutoff_rs", [4.5, 3.0, 6.0])
+def test_split_table_matches_erfc_split(b, cutoff_rs):
+    """The FP32 pair sum's table of f(u) = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
+    evaluated the way the kernel does (FP32, bin = floor(r B / r_c)), agrees
+    with SciPy's erfc to FP32 rounding over the whole range [0, r_c)."""
+    import numpy as np
+    from scipy.special import erfc
+    tab = b.split_table(cutoff_rs)
+    B = tab.shape[1] - 1
+    assert tab.shape == (4, B + 1) and tab.dtype == np.float32
+    u_c = 0.5 * cutoff_rs
+    u = np.linspace(0.0, u_c, 200001)
+    x = (u / u_c * B).astype(np.float32)
+    k = np.minimum(x.astype(np.int64), B)
+    t = x - k.astype(np.float32)
+    c = [tab[l][k] for l in range(4)]
+    f32 = c[0] + t * (c[1] + t * (c[2] + t * c[3]))
+    ref = erfc(u) + 2.0 / np.sqrt(np.pi) * u * np.exp(-u * u)
+    assert np.max(np.abs(f32 - ref)) < 3e-7
+    assert tab[0][B] == np.float32(erfc(u_c) + 2.0 / np.sqrt(np.pi) * u_c * np.exp(-u_c ** 2))
+    assert np.all(tab[1:, B] == 0)
+    # neighbouring pieces meet: the end of bin k is the start of bin k + 1
+    ends = tab[0][:B] + tab[1][:B] + tab[2][:B] + tab[3][:B]
+    assert np.max(np.abs(ends - tab[0][1:])) < 2e-7
+
+
+def test_split_table_rejects_bad_arguments(b):
+    f = b._lib.p3m_split_table
+    assert f(0.0, None, 0) == -1
+    assert f(float("nan"), None, 0) == -1
+    assert f(4.5, None, 8) == -1
+    assert f(4.5, None, 0) > 0
