@@ -25,19 +25,31 @@ extern "C" {
 int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out,
                          int32_t cap);
 
-/* Table of the split factor f(u) = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
- * u = r / (2 r_s), that the FP32 pair sum evaluates: u in [0, cutoff_rs / 2]
- * is cut into B equal bins, and bin k holds the cubic
- * c0 + c1 t + c2 t^2 + c3 t^3 (t in [0, 1] across the bin) through f at the
- * four Chebyshev points of the bin; entry B is the constant f at the cutoff.
- * Layout: out[c * (B + 1) + k] for c = 0..3, k = 0..B. Returns B and writes
- * the 4 (B + 1) floats when cap >= 4 (B + 1) (out may be NULL with cap == 0).
- * P3M_EINVAL (-1) for cutoff_rs <= 0 or non-finite, or cap > 0 with NULL out. */
-int32_t p3m_split_table(double cutoff_rs, float* out, int32_t cap);
+/* Table of the split factor f = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
+ * u = r / (2 r_s), that the FP32 pair sum evaluates (P3M short-range force,
+ * CONCEPT User's Guide, Ch. 5: P3M_scale, P3M_cutoff, softening). Arguments:
+ * cutoff_rs = r_c / r_s, softening_rs = eps / r_s.
+ *
+ * The table variable v (in units of r_s) is the softened distance
+ * sqrt(r^2 + eps^2) / r_s when cubic pieces of f over it stay within 1e-7 of
+ * f (f has a kink at r = 0, which only pieces that are wide against eps
+ * follow), else r / r_s. [v0, v1] is cut into B equal bins; with
+ * x = (v - v0) B / (v1 - v0), k = floor(x), t = x - k, the table gives
+ * f = c0[k] + t (c1[k] + t (c2[k] + t c3[k])), the cubic through f at the four
+ * Chebyshev points of bin k; entry B is the constant f at v1 (for arguments
+ * rounded up onto the cutoff).
+ *
+ * Layout: out[c * (B + 1) + k] for c = 0..3, k = 0..B; map_out (may be NULL)
+ * receives {variable (0: r, 1: softened distance), v0, v1}. Returns B and
+ * writes the 4 (B + 1) floats and the map when cap >= 4 (B + 1) (out may be
+ * NULL with cap == 0). P3M_EINVAL (-1) for cutoff_rs <= 0, softening_rs < 0,
+ * a non-finite argument, or cap > 0 with NULL out. */
+int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32_t cap,
+                        double* map_out);
 
 /* Edge, in cells, of the i-groups the pair sum uses for n particles on a
  * grid of grid_n^3 cells: the power of two (1, 2 or 4) closest to a mean of
- * 8 particles per group, never larger than grid_n / 2. */
+ * 64 particles per group, never larger than grid_n / 2. */
 int32_t p3m_group_edge(int64_t n, int32_t grid_n);
 
 /* Background cosmology for comoving kick and drift coefficients (CONCEPT

@@ -66,7 +66,8 @@ def _load():
         "p3m_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "p3m_stencil_rows": (i32, [i32, dbl, ctypes.POINTER(i32), i32]),
         "p3m_group_edge": (i32, [i64, i32]),
-        "p3m_split_table": (i32, [dbl, ctypes.POINTER(ctypes.c_float), i32]),
+        "p3m_split_table": (i32, [dbl, dbl, ctypes.POINTER(ctypes.c_float), i32,
+                                  ctypes.POINTER(dbl)]),
         "p3m_cosmo_age": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
                                          ctypes.POINTER(dbl)]),
         "p3m_cosmo_scale_factor": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
@@ -136,15 +137,20 @@ def group_edge(n: int, grid_n: int) -> int:
     return int(_lib.p3m_group_edge(n, grid_n))
 
 
-def split_table(cutoff_rs: float):
+def split_table(cutoff_rs: float, softening_rs: float = 0.0):
     """FP32 split-factor table of the pair sum: a (4, B + 1) float32 array of
-    cubic coefficients c0..c3 per bin of u in [0, cutoff_rs / 2]."""
+    cubic coefficients c0..c3 per bin, and the map (variable, v0, v1): the
+    variable is 0 for r / r_s, 1 for sqrt(r^2 + eps^2) / r_s, and the bins cut
+    [v0, v1] evenly."""
     import numpy as np
-    b = _lib.p3m_split_table(cutoff_rs, None, 0)
+    b = _lib.p3m_split_table(cutoff_rs, softening_rs, None, 0, None)
     _check(min(b, 0), "p3m_split_table")
     buf = (ctypes.c_float * (4 * (b + 1)))()
-    _lib.p3m_split_table(cutoff_rs, buf, 4 * (b + 1))
-    return np.frombuffer(buf, dtype=np.float32).reshape(4, b + 1).copy()
+    m = (ctypes.c_double * 3)()
+    _check(min(_lib.p3m_split_table(cutoff_rs, softening_rs, buf, 4 * (b + 1), m), 0),
+           "p3m_split_table")
+    tab = np.frombuffer(buf, dtype=np.float32).reshape(4, b + 1).copy()
+    return tab, (int(m[0]), float(m[1]), float(m[2]))
 
 
 @dataclass(frozen=True)

@@ -1,6 +1,7 @@
 // The C ABI of libp3m.so: argument checking, plan geometry and workspace,
 // and the order of the force stages. Declared in include/p3m.h and
 // include/p3m_host.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -155,35 +156,71 @@ static double split_f(double u) {
   return std::erfc(u) + 1.1283791670955126 * u * std::exp(-u * u);
 }
 
-void split_table(double u_c, int bins, float* out) {
-  // Bin k covers u = (k + t) u_c / bins, t in [0, 1]: the cubic through f at
-  // the four Chebyshev points of [0, 1] (4x4 Vandermonde solve). Entry `bins`
-  // is the constant f(u_c), for arguments rounded up onto the cutoff.
+// f as a function of the table variable v (in units of r_s): v = r / r_s, or
+// v = sqrt(r^2 + eps^2) / r_s (e = eps / r_s; values below e never occur and
+// take f(0)).
+static double split_g(int var, double e, double v) {
+  if (var == 0) return split_f(0.5 * v);
+  return split_f(0.5 * std::sqrt(std::max(v * v - e * e, 0.0)));
+}
+
+// Cubic pieces of g over [v0, v1] (FP64 coefficients) and their largest
+// deviation from g on a dense sample.
+static double fit_table(int var, double e, double v0, double v1, int bins, double* c) {
   const double kPi = 3.14159265358979323846;
-  const int stride = bins + 1;
+  const double w = (v1 - v0) / bins;
+  double worst = 0;
   for (int k = 0; k < bins; ++k) {
+    // the cubic in t through g at the four Chebyshev points of [0, 1]
     double V[4][5];
     for (int j = 0; j < 4; ++j) {
       double t = 0.5 - 0.5 * std::cos((2 * j + 1) * kPi / 8.0);
       double p = 1.0;
       for (int l = 0; l < 4; ++l, p *= t) V[j][l] = p;
-      V[j][4] = split_f((k + t) * u_c / bins);
+      V[j][4] = split_g(var, e, v0 + (k + t) * w);
     }
-    for (int c = 0; c < 4; ++c) {           // Gauss-Jordan, partial pivoting
-      int piv = c;
-      for (int r = c + 1; r < 4; ++r)
-        if (std::fabs(V[r][c]) > std::fabs(V[piv][c])) piv = r;
-      for (int l = 0; l < 5; ++l) std::swap(V[c][l], V[piv][l]);
+    for (int col = 0; col < 4; ++col) {     // Gauss-Jordan, partial pivoting
+      int piv = col;
+      for (int r = col + 1; r < 4; ++r)
+        if (std::fabs(V[r][col]) > std::fabs(V[piv][col])) piv = r;
+      for (int l = 0; l < 5; ++l) std::swap(V[col][l], V[piv][l]);
       for (int r = 0; r < 4; ++r) {
-        if (r == c) continue;
-        double m = V[r][c] / V[c][c];
-        for (int l = c; l < 5; ++l) V[r][l] -= m * V[c][l];
+        if (r == col) continue;
+        double m = V[r][col] / V[col][col];
+        for (int l = col; l < 5; ++l) V[r][l] -= m * V[col][l];
       }
     }
-    for (int l = 0; l < 4; ++l) out[l * stride + k] = (float)(V[l][4] / V[l][l]);
+    for (int l = 0; l < 4; ++l) c[4 * k + l] = V[l][4] / V[l][l];
+    for (int j = 0; j <= 64; ++j) {
+      double t = j / 64.0;
+      double f = c[4 * k] + t * (c[4 * k + 1] + t * (c[4 * k + 2] + t * c[4 * k + 3]));
+      worst = std::max(worst, std::fabs(f - split_g(var, e, v0 + (k + t) * w)));
+    }
   }
-  out[0 * stride + bins] = (float)split_f(u_c);
+  return worst;
+}
+
+SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out) {
+  // Prefer the softened distance as the variable (no square root in the pair
+  // loop); it has a kink at v = e, which a cubic piece follows only while e
+  // is small against the bin width, so fall back to r when the fit misses
+  // the bound. The start sits a hair below e so that rounding never takes
+  // the kernel's bin coordinate below zero.
+  const double kFitBound = 1e-7;
+  double c[4 * kSplitBins];
+  bins = std::min(bins, kSplitBins);
+  SplitMap m{1, soft_rs * (1.0 - 1e-6), std::sqrt(cutoff_rs * cutoff_rs + soft_rs * soft_rs)};
+  if (fit_table(m.var, soft_rs, m.v0, m.v1, bins, c) > kFitBound) {
+    m = SplitMap{0, 0.0, cutoff_rs};
+    fit_table(m.var, soft_rs, m.v0, m.v1, bins, c);
+  }
+  const int stride = bins + 1;
+  for (int k = 0; k < bins; ++k)
+    for (int l = 0; l < 4; ++l) out[l * stride + k] = (float)c[4 * k + l];
+  // entry `bins`: the constant g(v1), for arguments rounded up onto the cutoff
+  out[0 * stride + bins] = (float)split_g(m.var, soft_rs, m.v1);
   out[1 * stride + bins] = out[2 * stride + bins] = out[3 * stride + bins] = 0.0f;
+  return m;
 }
 
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
@@ -229,10 +266,19 @@ int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out, int3
   return p3m::stencil_rows(g, radius_cells, rows_out, cap);
 }
 
-int32_t p3m_split_table(double cutoff_rs, float* out, int32_t cap) {
-  if (!(cutoff_rs > 0) || !std::isfinite(cutoff_rs) || cap < 0 || (cap > 0 && !out))
+int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32_t cap,
+                        double* map_out) {
+  if (!(cutoff_rs > 0) || !std::isfinite(cutoff_rs) || !(softening_rs >= 0) ||
+      !std::isfinite(softening_rs) || cap < 0 || (cap > 0 && !out))
     return P3M_EINVAL;
-  if (cap >= 4 * (kSplitBins + 1)) p3m::split_table(0.5 * cutoff_rs, kSplitBins, out);
+  if (cap >= 4 * (kSplitBins + 1)) {
+    p3m::SplitMap m = p3m::split_table(cutoff_rs, softening_rs, kSplitBins, out);
+    if (map_out) {
+      map_out[0] = m.var;
+      map_out[1] = m.v0;
+      map_out[2] = m.v1;
+    }
+  }
   return kSplitBins;
 }
 
@@ -342,7 +388,10 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   }
   if (err == hipSuccess) {
     float tab[4 * (kSplitBins + 1)];
-    split_table(0.5 * q.cutoff_rs, kSplitBins, tab);     // u_c = r_c / (2 r_s)
+    SplitMap m = split_table(q.cutoff_rs, q.softening / r_s, kSplitBins, tab);
+    P->tab_var = m.var;
+    P->tab_v0 = m.v0 * r_s;
+    P->tab_v1 = m.v1 * r_s;
     err = hipMemcpy(W.split_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
   }
   if (err == hipSuccess)

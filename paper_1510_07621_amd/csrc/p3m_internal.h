@@ -69,6 +69,8 @@ struct p3m_plan {
   int64_t ngroup = 0;
   int nrows = 0;
   int64_t max_items = 0;
+  int tab_var = 0;              // FP32 split table: variable (0: r, 1: softened r)
+  double tab_v0 = 0, tab_v1 = 0;  // and its range, as lengths
   int scan_tmp_len = 0;
   p3m::Workspace ws;
   // stage timers: events [call][2 * stage + {0: start, 1: end}]
@@ -112,7 +114,13 @@ hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double*
 
 // Host geometry helpers.
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap);
-// Split-factor table: out[c * (bins + 1) + k] is coefficient c of bin k.
-void split_table(double u_c, int bins, float* out);
+// Split-factor table: out[c * (bins + 1) + k] is coefficient c of bin k of
+// the cubic pieces over v in [v0, v1] (units of r_s); var 0: v = r / r_s,
+// var 1: v = sqrt(r^2 + eps^2) / r_s.
+struct SplitMap {
+  int var;
+  double v0, v1;
+};
+SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out);
 
 }  // namespace p3m

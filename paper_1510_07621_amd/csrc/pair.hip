@@ -4,8 +4,8 @@
 //   f(r) = erfc(u) + (2u / sqrt(pi)) exp(-u^2),  u = r / (2 r_s)
 //
 // Work decomposition. The grid's cells are grouped into i-groups of G^3
-// cells; a work item is (group, chunk) with up to 64 of the group's
-// particles, one wavefront per item. The j-candidates of a group are the
+// cells; a work item is (group, chunk) with up to kChunk (128) of the
+// group's particles, one wavefront per item. The j-candidates of a group are the
 // particles of every cell whose box comes closer than r_c to the group's box
 // (the stencil rows: z-runs of cells, precomputed per plan).
 //
@@ -14,8 +14,8 @@
 // scarce resource of a cutoff test. With n_i particles the wave has
 // n_u = ceil(n_i / U) slot-sets and s = 64 / n_u streams: lane (set, stream)
 // takes every s-th staged j, so small groups still fill the wave, and the s
-// partial sums of each i are added at the end. U = 4, or 1 for an item with a
-// single particle.
+// partial sums of each i are added at the end. FP32: U = 8 above 64
+// particles, else 4; FP64: U = 2; U = 1 for an item with a single particle.
 //
 // Staging. Per batch of 64 stencil rows each lane resolves one row into at
 // most three contiguous sorted runs (the z-run split where it crosses the
@@ -25,11 +25,15 @@
 // rebuilt from cell-relative offsets and small integer cell differences, so
 // the FP32 path never subtracts two large coordinates.
 //
-// Arithmetic. FP32: rsq(r^2 + eps^2), sqrt(r^2), and f from a table of 64
-// cubic pieces over [0, r_c) held in LDS (fitted in FP64 by the plan at the
-// Chebyshev points of each piece; error well below FP32 rounding), so a pair
-// costs two transcendentals instead of four. FP64: the device library's erfc,
-// exp, sqrt and rsqrt.
+// Arithmetic. FP32: rsq(r^2 + eps^2) and f from a table of 64 cubic pieces
+// held in LDS, fitted in FP64 by the plan at the Chebyshev points of each
+// piece (error below 1e-7). The table's variable is the softened distance
+// sqrt(r^2 + eps^2), which rsq already yields, so a pair costs a single
+// transcendental; when eps is too large against a piece for the cubic to
+// follow the kink at r = 0, the plan tabulates over r and a square root is
+// added. FP64: the device library's erfc, exp, sqrt and rsqrt.
+#include <algorithm>
+
 #include "p3m_internal.h"
 
 namespace p3m {
@@ -51,9 +55,15 @@ struct PairArgs {
   const int4* __restrict__ rows;
   int nrows;
   int ng, lg, G, lgG;
-  T h, rc2, eps2, inv2rs, negG;
-  const float* __restrict__ split_tab;  // FP32 split-factor table [4][kSplitBins + 1]
-  float xscale;                         // kSplitBins / r_c
+  T h, rc2;
+  T eps2, inv2rs;                       // FP64 weight
+  // FP32 weight from the split table: with s = kSplitBins / (v1 - v0) per
+  // length, q = s^2 (r^2 + eps^2), the bin coordinate is x = q rsq(q) - s v0
+  // (softened variable) or x = s r (plain r), and the returned weight is
+  // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
+  const float* __restrict__ split_tab;  // [4][kSplitBins + 1]
+  float tab_s, tab_s2, tab_e2, tab_off;
+  double wscale;                        // -G, times s^3 on the FP32 path
   const typename Vec<T>::v4* __restrict__ acc_pm;  // sorted PM acceleration or null
   const int32_t* __restrict__ perm;
   int64_t n;
@@ -69,26 +79,33 @@ struct SplitTable {
   float c[4][kTabStride];
 };
 
-// f(r) / (r^2 + eps^2)^(3/2) for 0 <= r < r_c (r = 0 is masked by the caller).
-// FP32: f from the plan's piecewise-cubic table over x = r * kSplitBins / r_c.
+// f(r) / (r^2 + eps^2)^(3/2) for 0 <= r < r_c, up to the factor folded into
+// wscale. Self pairs (r = 0) give a finite weight times a zero separation.
+// FP32: f from the table, TAB selecting the variable (1: softened distance).
+// The squared scaled radius is floored at 1e-12 bins^2 (a radius a million
+// times below a bin, beneath FP32 position resolution), which keeps the
+// weight finite at r = 0 when eps = 0.
+template <int TAB>
 __device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
                                              const SplitTable& tab) {
-  float inv = __builtin_amdgcn_rsqf(r2 + A.eps2);
-  float inv3 = inv * inv * inv;
-  float x = __builtin_amdgcn_sqrtf(r2) * A.xscale;
-  int k = (int)x;                       // < kSplitBins + 1 since r < r_c
-  float t = x - (float)k;
-  float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
-  return f * inv3;
+  const float q = __builtin_fmaf(r2, A.tab_s2, A.tab_e2);
+  const float inv = __builtin_amdgcn_rsqf(q);
+  const float x = TAB ? __builtin_fmaf(q, inv, -A.tab_off)
+                      : __builtin_amdgcn_sqrtf(r2) * A.tab_s;   // >= 0
+  const int k = (int)x;                 // <= kSplitBins since r < r_c
+  const float t = __builtin_amdgcn_fractf(x);
+  const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
+  return f * (inv * inv * inv);
 }
 
+template <int TAB>
 __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>& A,
                                               const SplitTable&) {
   const double kTwoOverSqrtPi = 1.1283791670955126;
   double inv = rsqrt(r2 + A.eps2);
   double u = sqrt(r2) * A.inv2rs;
   double f = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
-  return f * (inv * inv * inv);
+  return r2 > 0.0 ? f * (inv * inv * inv) : 0.0;   // eps may be 0
 }
 
 __device__ __forceinline__ int wave_inclusive(int v) {
@@ -103,12 +120,13 @@ __device__ __forceinline__ int wave_inclusive(int v) {
 
 template <typename T>
 struct PairShared {
+  SplitTable tab;                          // FP32 path only; first, so one address
+                                           // register reaches all four arrays
   typename Vec<T>::v4 jb[kPairCap + 64];   // staged j (+ far sentinels); reused for the reduction
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
   int owner[kPairCap];                     // run of each staged entry of a chunk
   T d_sx[64], d_sy[64];
   int i_lo[16], i_pre[17];
-  SplitTable tab;                          // FP32 path only
 };
 
 // One stencil row (per lane) resolved into at most three contiguous sorted
@@ -154,7 +172,7 @@ __device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, int rb,
 
 // One work item with U i-slots per lane. UM: every particle has the same mass
 // (mass applied once at the end instead of per pair).
-template <typename T, int U, bool COUNT, bool UM>
+template <typename T, int U, bool COUNT, bool UM, int TAB>
 __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S, int gx0,
                                           int gy0, int gz0, int ibeg, int ni) {
   using T4 = typename Vec<T>::v4;
@@ -305,9 +323,8 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
             if (COUNT) {
               npairs += r2 > T(0) ? 1 : 0;
             } else {
-              T w = pair_weight(r2, A, S.tab);
+              T w = pair_weight<TAB>(r2, A, S.tab);
               if (!UM) w *= pj.w;
-              w = r2 > T(0) ? w : T(0);      // zero separation: no contribution
               ax[u] += w * dx;
               ay[u] += w * dy;
               az[u] += w * dz;
@@ -351,30 +368,30 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
     while (run + 1 < GG && S.i_pre[run + 1] <= fi) ++run;
     const int s = S.i_lo[run] + (fi - S.i_pre[run]);
     const double m = (double)A.rec[s].w;
-    T gx = A.negG * sx, gy = A.negG * sy, gz = A.negG * sz;
+    double gx = A.wscale * (double)sx, gy = A.wscale * (double)sy, gz = A.wscale * (double)sz;
     if (UM) {
-      gx *= T(m); gy *= T(m); gz *= T(m);
+      gx *= m; gy *= m; gz *= m;
     }
     if (A.acc_pm) {
       const T4 pm = A.acc_pm[s];
-      gx += pm.x; gy += pm.y; gz += pm.z;
+      gx += (double)pm.x; gy += (double)pm.y; gz += (double)pm.z;
     }
     const int64_t i = A.perm[s];
     if (A.force_fp32) {
       float* F = (float*)A.force;
-      F[i] = (float)(m * (double)gx);
-      F[A.n + i] = (float)(m * (double)gy);
-      F[2 * A.n + i] = (float)(m * (double)gz);
+      F[i] = (float)(m * gx);
+      F[A.n + i] = (float)(m * gy);
+      F[2 * A.n + i] = (float)(m * gz);
     } else {
       double* F = (double*)A.force;
-      F[i] = m * (double)gx;
-      F[A.n + i] = m * (double)gy;
-      F[2 * A.n + i] = m * (double)gz;
+      F[i] = m * gx;
+      F[A.n + i] = m * gy;
+      F[2 * A.n + i] = m * gz;
     }
   }
 }
 
-template <typename T, bool COUNT, bool UM>
+template <typename T, bool COUNT, bool UM, int TAB>
 __global__ void __launch_bounds__(64)
 k_pairs(PairArgs<T> A) {
   __shared__ PairShared<T> S;
@@ -416,13 +433,13 @@ k_pairs(PairArgs<T> A) {
   const int ni = min(kChunk, ntot - ibeg);
   // i-slots per lane: enough that ceil(ni / U) slot sets fit in the wave
   if (ni == 1)
-    pair_item<T, 1, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 1, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
   else if (sizeof(T) == 8)
-    pair_item<T, 2, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 2, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
   else if (ni <= 64)
-    pair_item<T, 4, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 4, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
   else
-    pair_item<T, 8, COUNT, UM>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 8, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
 }
 
 // Grid of the pair kernel: the item bound rounded up to a multiple of kXcds.
@@ -449,9 +466,16 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.rc2 = (T)(P->r_c * P->r_c);
   A.eps2 = (T)(P->eps * P->eps);
   A.inv2rs = (T)(1.0 / (2.0 * P->r_s));
-  A.negG = (T)(-P->prm.G);
-  A.split_tab = W.split_tab;
-  A.xscale = (float)(kSplitBins / P->r_c);
+  A.wscale = -P->prm.G;
+  if (sizeof(T) == 4) {
+    const double s = kSplitBins / (P->tab_v1 - P->tab_v0);
+    A.split_tab = W.split_tab;
+    A.tab_s = (float)s;
+    A.tab_s2 = (float)(s * s);
+    A.tab_e2 = (float)std::max(s * s * P->eps * P->eps, 1e-12);
+    A.tab_off = (float)(s * P->tab_v0);
+    A.wscale *= s * s * s;
+  }
   A.perm = W.perm;
   A.n = n;
   return A;
@@ -467,10 +491,19 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
   A.force = force_out;
   A.force_fp32 = force_fp32;
   const unsigned grid = pair_grid(P);
+  if constexpr (sizeof(T) == 4) {
+    if (P->tab_var == 1) {            // split table over the softened distance
+      if (uniform_mass)
+        k_pairs<T, false, true, 1><<<grid, 64, 0, P->stream>>>(A);
+      else
+        k_pairs<T, false, false, 1><<<grid, 64, 0, P->stream>>>(A);
+      return hipGetLastError();
+    }
+  }
   if (uniform_mass)
-    k_pairs<T, false, true><<<grid, 64, 0, P->stream>>>(A);
+    k_pairs<T, false, true, 0><<<grid, 64, 0, P->stream>>>(A);
   else
-    k_pairs<T, false, false><<<grid, 64, 0, P->stream>>>(A);
+    k_pairs<T, false, false, 0><<<grid, 64, 0, P->stream>>>(A);
   return hipGetLastError();
 }
 
@@ -480,7 +513,7 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
   A.counter = (unsigned long long*)count_out;
   hipError_t e = launch_fill_i32((int32_t*)count_out, 2, 0, P->stream);
   if (e != hipSuccess) return e;
-  k_pairs<T, true, true><<<pair_grid(P), 64, 0, P->stream>>>(A);
+  k_pairs<T, true, true, 0><<<pair_grid(P), 64, 0, P->stream>>>(A);
   return hipGetLastError();
 }
 

@@ -155,26 +155,45 @@ def test_group_edge(b):
     assert b.group_edge(10 ** 9, 16) == 1
 
 
-@pytest.mark.parametrize("cutoff_rs", [4.5, 3.0, 6.0])
-def test_split_table_matches_erfc_split(b, cutoff_rs):
-    """The FP32 pair sum's table of f(u) = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
-    evaluated the way the kernel does (FP32, bin = floor(r B / r_c)), agrees
-    with SciPy's erfc to FP32 rounding over the whole range [0, r_c)."""
-    import numpy as np
+def _split_f(u):
     from scipy.special import erfc
-    tab = b.split_table(cutoff_rs)
+    import numpy as np
+    return erfc(u) + 2.0 / np.sqrt(np.pi) * u * np.exp(-u * u)
+
+
+@pytest.mark.parametrize("cutoff_rs,soft_rs,var", [
+    (4.5, 0.0, 1),          # no softening: the softened distance is r itself
+    (4.5, 0.024, 1),        # 0.03 mean spacing at r_s = 1.25 cells
+    (3.0, 0.024, 1),
+    (6.0, 0.01, 1),
+    (4.5, 0.08, 0),         # eps wide against a bin: the kink forces r
+    (4.5, 0.8, 0),
+])
+def test_split_table_matches_erfc_split(b, cutoff_rs, soft_rs, var):
+    """The FP32 pair sum's table of f(u) = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
+    u = r / (2 r_s), looked up the way the kernel does (FP32 bin coordinate,
+    bin = floor, entry B past the cutoff), agrees with SciPy's erfc to FP32
+    rounding over all of 0 <= r < r_c."""
+    import numpy as np
+    tab, (v, v0, v1) = b.split_table(cutoff_rs, soft_rs)
     B = tab.shape[1] - 1
     assert tab.shape == (4, B + 1) and tab.dtype == np.float32
-    u_c = 0.5 * cutoff_rs
-    u = np.linspace(0.0, u_c, 200001)
-    x = (u / u_c * B).astype(np.float32)
-    k = np.minimum(x.astype(np.int64), B)
+    assert v == var
+    r = np.linspace(0.0, cutoff_rs, 400001)[:-1]            # units of r_s
+    rho = np.sqrt(r * r + soft_rs * soft_rs) if v == 1 else r
+    if v == 1:
+        assert soft_rs * (1 - 2e-6) <= v0 <= soft_rs
+        assert v1 == pytest.approx(np.hypot(cutoff_rs, soft_rs), rel=1e-15)
+    else:
+        assert (v0, v1) == (0.0, cutoff_rs)
+    x = ((rho - v0) * (B / (v1 - v0))).astype(np.float32)
+    assert x.min() >= 0 and x.max() < B + 1
+    k = x.astype(np.int64)
     t = x - k.astype(np.float32)
     c = [tab[l][k] for l in range(4)]
     f32 = c[0] + t * (c[1] + t * (c[2] + t * c[3]))
-    ref = erfc(u) + 2.0 / np.sqrt(np.pi) * u * np.exp(-u * u)
-    assert np.max(np.abs(f32 - ref)) < 3e-7
-    assert tab[0][B] == np.float32(erfc(u_c) + 2.0 / np.sqrt(np.pi) * u_c * np.exp(-u_c ** 2))
+    assert np.max(np.abs(f32 - _split_f(0.5 * r))) < 2.5e-7
+    assert tab[0][B] == np.float32(_split_f(0.5 * cutoff_rs))
     assert np.all(tab[1:, B] == 0)
     # neighbouring pieces meet: the end of bin k is the start of bin k + 1
     ends = tab[0][:B] + tab[1][:B] + tab[2][:B] + tab[3][:B]
@@ -183,7 +202,9 @@ def test_split_table_matches_erfc_split(b, cutoff_rs):
 
 def test_split_table_rejects_bad_arguments(b):
     f = b._lib.p3m_split_table
-    assert f(0.0, None, 0) == -1
-    assert f(float("nan"), None, 0) == -1
-    assert f(4.5, None, 8) == -1
-    assert f(4.5, None, 0) > 0
+    assert f(0.0, 0.0, None, 0, None) == -1
+    assert f(float("nan"), 0.0, None, 0, None) == -1
+    assert f(4.5, -0.1, None, 0, None) == -1
+    assert f(4.5, float("inf"), None, 0, None) == -1
+    assert f(4.5, 0.0, None, 8, None) == -1
+    assert f(4.5, 0.0, None, 0, None) > 0

@@ -119,6 +119,31 @@ def test_pp_force_parity(uniform32, precision, tol):
     assert e["rms"] <= tol, e
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("soft_cells", [0.0, 0.03, 0.3, 1.0])
+def test_pp_force_parity_across_softening(precision, tol, soft_cells):
+    """The short-range sum for no softening, the default (0.03 mean spacing)
+    and softenings wide against a split-table bin, where the FP32 table is
+    taken over r instead of the softened distance; close pairs (0.05-0.2
+    cells apart) included."""
+    from paper_1510_07621_amd import binding
+    grid = 16
+    h = 1.0 / grid
+    rng = np.random.default_rng(31)
+    base = ics.uniform(3500, seed=32)
+    near = (base[:, :300] + rng.uniform(0.05, 0.2, (3, 300)) * h) % 1.0
+    pos = np.concatenate([base, near], axis=1)
+    eps = soft_cells * h
+    _, (var, _, _) = binding.split_table(4.5, eps / (1.25 * h))
+    assert var == (1 if soft_cells <= 0.03 else 0)
+    m = 1.0 / pos.shape[1]
+    ref = o_pp.pp_accel(pos, m, 1.0, 1.25 * h, 4.5 * 1.25 * h, eps, 1.0) * m
+    with plan(grid, pos.shape[1], precision, softening=eps) as P:
+        F = host(P.pp_force(dev(pos), m))
+    e = _err(F, ref)
+    assert e["rms"] <= tol, e
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_pm_force_parity(uniform32, precision, tol):
     w, pos, _, a_pm = uniform32
