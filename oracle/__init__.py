@@ -20,9 +20,11 @@ ewald      O-EW: direct periodic summation by the Ewald method (the truth)
 integrate  kick and drift updates
 metrics    per-particle relative force-error statistics
 cosmology  background expansion and the comoving kick/drift coefficients
+adjoint    VJP of the force (pair Hessian-vector sum; mesh adjoint) and of
+           the kick-drift-kick leapfrog
 
 Array conventions: positions, momenta, accelerations and forces are float64
 arrays of shape (3, N) (structure of arrays, as in the guide's snapshot
 layout); masses are a float64 array of shape (N,) or a scalar.
 """
-from . import split, pp, pm, p3m, ewald, integrate, metrics, cosmology  # noqa: F401
+from . import split, pp, pm, p3m, ewald, integrate, metrics, cosmology, adjoint  # noqa: F401
