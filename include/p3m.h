@@ -70,6 +70,7 @@ typedef struct p3m_params {
   double  cutoff_rs;    /* P3M_cutoff: r_c in units of r_s, > 0 (4.5 typical)        */
   double  softening;    /* Plummer radius eps as a length, >= 0                      */
   double  G;            /* gravitational constant                                    */
+  int32_t adjoint;      /* 1: also allocate the workspace of the *_force_vjp calls   */
 } p3m_params;
 
 /* Opaque plan: derived geometry, device workspace, and optional stage timers. */
@@ -77,14 +78,17 @@ typedef struct p3m_plan p3m_plan;
 
 /* Fill *out with the documented defaults for a grid of grid_n^3 cells in a
  * box of side box: FP32, fd_order 4, deconv_power 2, rs_cells 1.25,
- * cutoff_rs 4.5, softening 0, G 1. Returns P3M_EINVAL for a null out. */
+ * cutoff_rs 4.5, softening 0, G 1, adjoint 0. Returns P3M_EINVAL for a null
+ * out. */
 int p3m_params_default(p3m_params* out, int32_t grid_n, double box);
 
 /* Create a plan for up to n_max particles whose work runs on hip_stream
  * (a hipStream_t; NULL = the null stream). Validates the parameters
  * (EINVAL for a non-power-of-two or out-of-range grid, box <= 0,
- * rs_cells <= 0, cutoff_rs <= 0, softening < 0, n_max < 0 or
- * n_max >= 2^31; ERANGE when r_c >= box/2), then allocates the workspace
+ * rs_cells <= 0, cutoff_rs <= 0, softening < 0, adjoint not 0 or 1,
+ * n_max < 0 or n_max >= 2^31; ERANGE when r_c >= box/2), then allocates the
+ * workspace (with adjoint = 1 also that of the VJP calls: one more real grid,
+ * three cotangent grids and a sorted cotangent array)
  * (ENOMEM on failure; nothing is leaked). *out is set only on success. */
 int p3m_plan_create(const p3m_params* params, int64_t n_max, void* hip_stream,
                     p3m_plan** out);
@@ -114,6 +118,35 @@ int pm_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
 int pp_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
              double mass_scalar, void* force, int32_t force_fp32);
 
+/* Adjoint of the force (vector-Jacobian product), for gradients through
+ * trajectories. The guide gives no derivatives; these are the exact
+ * transposes of the definitions above (away from the measure-zero sets where
+ * a pair crosses r_c or a particle crosses a node plane, where the force is
+ * not differentiable). For a cotangent lam on the force F:
+ *   pos_bar_k = sum_i lam_i . dF_i/dx_k.
+ * PP:  pos_bar_k = -G m_k sum_{j: 0 < r < r_c} m_j J(r_kj) (lam_k - lam_j),
+ *      J = g I + (g'(r)/r) r r^T, g = f / (r^2 + eps^2)^(3/2).
+ * PM:  pos_bar_k = m_k sum_c grad W(x_k - c) [h^-3 psi(c) - lam_k . E(c)],
+ *      E = D phi the node gradient of the forward potential,
+ *      psi = P (sum_d D_d Lam_d), Lam_d(c) = sum_i m_i lam_{i,d} W(x_i - c),
+ *      P the Green's function operator of the forward solve.
+ *   pos, mass, mass_scalar  as for p3m_force
+ *   force_bar   device, double [3][n] (input order)
+ *   pos_bar     device output, double [3][n], overwritten; must not overlap
+ *               pos, mass or force_bar
+ * The plan must have been created with params.adjoint = 1 (else EINVAL).
+ * The arithmetic is the plan's precision. n == 0 is a successful no-op. */
+int p3m_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+                  double mass_scalar, const double* force_bar, double* pos_bar);
+
+/* Adjoint of the long-range (PM) part only. Same arguments. */
+int pm_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+                 double mass_scalar, const double* force_bar, double* pos_bar);
+
+/* Adjoint of the short-range (PP) part only. Same arguments. */
+int pp_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+                 double mass_scalar, const double* force_bar, double* pos_bar);
+
 /* Count the ordered pairs (i, j != i) with minimum-image separation in
  * (0, r_c), the pairs the short-range sum evaluates (a diagnostic for
  * interaction rates). count_out: device int64 [1], overwritten. Separations
@@ -135,6 +168,16 @@ int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32,
  * [3][n]; mass: device double [n] or NULL for mass_scalar. box > 0. */
 int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
               double mass_scalar, double c_drift, double box, void* hip_stream);
+
+/* Transpose of the drift: x1 = wrap(x + c_drift p / m) has slope 1 in x and
+ * c_drift / m in p, so mom_bar <- mom_bar + (c_drift / m) * pos_bar (the
+ * quotient first, then one product and one sum per component, no fused
+ * multiply-add). mom_bar: device double [3][n] in place; pos_bar: device
+ * double [3][n], not overlapping mom_bar; mass: device double [n] or NULL for
+ * mass_scalar. (The kick's transpose needs no call: its force cotangent is
+ * c_kick * p_bar, passed to p3m_force_vjp by scaling its result.) */
+int p3m_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar, const double* mass,
+                  double mass_scalar, double c_drift, void* hip_stream);
 
 /* Stage timers. p3m_set_timing(plan, capacity) with capacity > 0 records HIP
  * events around the stages of the next `capacity` force calls, on the plan's

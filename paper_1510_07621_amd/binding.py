@@ -34,6 +34,7 @@ class P3MParams(ctypes.Structure):
         ("cutoff_rs", ctypes.c_double),
         ("softening", ctypes.c_double),
         ("G", ctypes.c_double),
+        ("adjoint", ctypes.c_int32),
     ]
 
 
@@ -59,6 +60,10 @@ def _load():
         "pm_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "pp_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "p3m_pair_count": (ctypes.c_int, [vp, i64, vp, vp]),
+        "p3m_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
+        "pm_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
+        "pp_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
+        "p3m_drift_vjp": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, vp]),
         "p3m_kick": (ctypes.c_int, [i64, vp, vp, i32, dbl, vp]),
         "p3m_drift": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, dbl, vp]),
         "p3m_set_timing": (ctypes.c_int, [vp, i32]),
@@ -211,6 +216,7 @@ class Params:
     precision: str = "fp32"      # "fp32" or "fp64"
     fd_order: int = 4
     deconv_power: int = 2
+    adjoint: bool = False        # also allocate the workspace of the VJP calls
 
     def to_c(self) -> P3MParams:
         if self.precision not in ("fp32", "fp64"):
@@ -219,7 +225,7 @@ class Params:
                          P3M_FP32 if self.precision == "fp32" else P3M_FP64,
                          int(self.fd_order), int(self.deconv_power), float(self.box),
                          float(self.rs_cells), float(self.cutoff_rs),
-                         float(self.softening), float(self.G))
+                         float(self.softening), float(self.G), 1 if self.adjoint else 0)
 
 
 class Plan:
@@ -282,6 +288,29 @@ class Plan:
     def pp_force(self, pos, mass=None, out=None, fp32_out=False):
         return self._force(_lib.pp_force, "pp_force", pos, mass, out, fp32_out)
 
+    def _vjp(self, fn, name, pos, mass, force_bar, out):
+        n = _vec3(pos, "pos")
+        if _vec3(force_bar, "force_bar") != n:
+            raise ValueError("force_bar must match pos")
+        m, ms = _mass(mass, n)
+        if out is None:
+            out = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        elif _vec3(out, "out") != n:
+            raise ValueError("out must be a (3, n) float64 tensor")
+        _check(fn(self._handle(), n, _ptr(pos), _ptr(m), ms, _ptr(force_bar), _ptr(out)), name)
+        return out
+
+    def force_vjp(self, pos, mass, force_bar, out=None):
+        """pos_bar = force_bar . dF/dpos of the full P3M force (plan made with
+        Params(adjoint=True)), shape (3, n) float64."""
+        return self._vjp(_lib.p3m_force_vjp, "p3m_force_vjp", pos, mass, force_bar, out)
+
+    def pm_force_vjp(self, pos, mass, force_bar, out=None):
+        return self._vjp(_lib.pm_force_vjp, "pm_force_vjp", pos, mass, force_bar, out)
+
+    def pp_force_vjp(self, pos, mass, force_bar, out=None):
+        return self._vjp(_lib.pp_force_vjp, "pp_force_vjp", pos, mass, force_bar, out)
+
     def pair_count(self, pos) -> int:
         """Ordered pairs with 0 < r < r_c (synchronises to return the count)."""
         n = _vec3(pos, "pos")
@@ -311,6 +340,17 @@ def kick(mom: torch.Tensor, force: torch.Tensor, c_kick: float) -> torch.Tensor:
     _check(_lib.p3m_kick(n, _ptr(mom), _ptr(force), 1 if force.dtype == torch.float32 else 0,
                          float(c_kick), _stream_ptr()), "p3m_kick")
     return mom
+
+
+def drift_vjp(mom_bar: torch.Tensor, pos_bar: torch.Tensor, mass, c_drift: float):
+    """Transpose of the drift: p_bar <- p_bar + (c_drift / m) x_bar in place."""
+    n = _vec3(mom_bar, "mom_bar")
+    if _vec3(pos_bar, "pos_bar") != n:
+        raise ValueError("pos_bar must match mom_bar")
+    m, ms = _mass(mass, n)
+    _check(_lib.p3m_drift_vjp(n, _ptr(mom_bar), _ptr(pos_bar), _ptr(m), ms, float(c_drift),
+                              _stream_ptr()), "p3m_drift_vjp")
+    return mom_bar
 
 
 def drift(pos: torch.Tensor, mom: torch.Tensor, mass, c_drift: float, box: float):

@@ -43,7 +43,8 @@ void free_workspace(p3m_plan* P) {
   Workspace& W = P->ws;
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
-                  W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab};
+                  W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.lam,
+                  W.grid2, W.lam_grid};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -144,6 +145,67 @@ int force_entry(p3m_plan* P, int64_t n, const double* pos, const double* mass, d
   hipError_t e = P->prm.precision == P3M_FP32
                      ? run_force<float>(P, n, pos, mass, ms, force, f32 ? 1 : 0, part)
                      : run_force<double>(P, n, pos, mass, ms, force, f32 ? 1 : 0, part);
+  return status_of(e);
+}
+
+// The adjoint stages. The two Poisson solves run on the same in-place FFT:
+// the forward potential phi in `grid`, then psi in `grid2` (buffers swapped
+// around the second solve).
+template <typename T>
+hipError_t run_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass, double ms,
+                   const double* fbar, double* pbar, Part part) {
+  hipError_t e;
+  Workspace& W = P->ws;
+  {
+    StageTimer t(P, P3M_STAGE_BIN);
+    if ((e = launch_bin(P, n, pos, mass, ms)) != hipSuccess) return e;
+    if (part != Part::kPM && (e = launch_items(P)) != hipSuccess) return e;
+    if ((e = launch_lambda_sort<T>(P, n, fbar)) != hipSuccess) return e;
+  }
+  if (part != Part::kPP) {
+    {
+      StageTimer t(P, P3M_STAGE_DEPOSIT);
+      if ((e = launch_deposit<T>(P)) != hipSuccess) return e;
+      if ((e = launch_deposit_lambda<T>(P)) != hipSuccess) return e;
+    }
+    {
+      StageTimer t(P, P3M_STAGE_FFT);
+      if ((e = launch_fft_poisson<T>(P)) != hipSuccess) return e;
+      std::swap(W.grid, W.grid2);
+      e = launch_fft_poisson<T>(P);
+      std::swap(W.grid, W.grid2);
+      if (e != hipSuccess) return e;
+    }
+    {
+      StageTimer t(P, P3M_STAGE_INTERP);
+      if ((e = launch_interp_vjp<T>(P, n, part == Part::kPM ? pbar : nullptr)) != hipSuccess)
+        return e;
+    }
+  }
+  if (part != Part::kPM) {
+    StageTimer t(P, P3M_STAGE_PP);
+    if ((e = launch_pairs_vjp<T>(P, n, part == Part::kP3M, pbar, mass == nullptr)) !=
+        hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+int vjp_entry(p3m_plan* P, int64_t n, const double* pos, const double* mass, double ms,
+              const double* fbar, double* pbar, Part part) {
+  if (!P || n < 0 || n > P->n_max) return P3M_EINVAL;
+  if (!P->prm.adjoint) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!pos || !fbar || !pbar) return P3M_EINVAL;
+  if (!mass && !std::isfinite(ms)) return P3M_EINVAL;
+  const size_t vbytes = (size_t)(3 * n) * sizeof(double);
+  if (overlaps(pbar, vbytes, pos, vbytes) || overlaps(pbar, vbytes, fbar, vbytes) ||
+      overlaps(pbar, vbytes, mass, (size_t)n * sizeof(double)))
+    return P3M_EINVAL;
+  begin_call(P);
+  hipError_t e = P->prm.precision == P3M_FP32
+                     ? run_vjp<float>(P, n, pos, mass, ms, fbar, pbar, part)
+                     : run_vjp<double>(P, n, pos, mass, ms, fbar, pbar, part);
   return status_of(e);
 }
 
@@ -326,6 +388,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   if (!(q.softening >= 0) || !std::isfinite(q.softening)) return P3M_EINVAL;
   if (!std::isfinite(q.G)) return P3M_EINVAL;
   if (n_max < 0 || n_max >= (int64_t{1} << 31)) return P3M_EINVAL;
+  if (q.adjoint != 0 && q.adjoint != 1) return P3M_EINVAL;
   const double h = q.box / q.grid_n;
   const double r_s = q.rs_cells * h;
   const double r_c = q.cutoff_rs * r_s;
@@ -375,6 +438,11 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   W.gtab = dev_alloc<unsigned char>(2 * q.grid_n * real, err);
   W.counter = dev_alloc<unsigned long long>(1, err);
   W.split_tab = dev_alloc<float>(4 * (kSplitBins + 1), err);
+  if (q.adjoint) {
+    W.lam = dev_alloc<unsigned char>(nn * 4 * real, err);
+    W.grid2 = dev_alloc<unsigned char>(P->ncell * real, err);
+    W.lam_grid = dev_alloc<unsigned char>(3 * P->ncell * real, err);
+  }
   if (err == hipSuccess) {
     int32_t* rows = new (std::nothrow) int32_t[4 * (size_t)P->nrows];
     if (!rows) {
@@ -436,6 +504,21 @@ int pp_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
   return force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kPP);
 }
 
+int p3m_force_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                  double mass_scalar, const double* force_bar, double* pos_bar) {
+  return vjp_entry(P, n, pos, mass, mass_scalar, force_bar, pos_bar, Part::kP3M);
+}
+
+int pm_force_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                 double mass_scalar, const double* force_bar, double* pos_bar) {
+  return vjp_entry(P, n, pos, mass, mass_scalar, force_bar, pos_bar, Part::kPM);
+}
+
+int pp_force_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                 double mass_scalar, const double* force_bar, double* pos_bar) {
+  return vjp_entry(P, n, pos, mass, mass_scalar, force_bar, pos_bar, Part::kPP);
+}
+
 int p3m_pair_count(p3m_plan* P, int64_t n, const double* pos, int64_t* count_out) {
   if (!P || n < 0 || n > P->n_max || !count_out) return P3M_EINVAL;
   if (n > 0 && !pos) return P3M_EINVAL;
@@ -467,6 +550,19 @@ int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
   if (!mass && !(mass_scalar != 0 && std::isfinite(mass_scalar))) return P3M_EINVAL;
   return status_of(launch_drift(n, pos, mom, mass, mass_scalar, c_drift, box,
                                 (hipStream_t)hip_stream));
+}
+
+int p3m_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar, const double* mass,
+                  double mass_scalar, double c_drift, void* hip_stream) {
+  if (n < 0) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!mom_bar || !pos_bar || !std::isfinite(c_drift)) return P3M_EINVAL;
+  if (!mass && !(mass_scalar != 0 && std::isfinite(mass_scalar))) return P3M_EINVAL;
+  if (overlaps(mom_bar, (size_t)(3 * n) * sizeof(double), pos_bar,
+               (size_t)(3 * n) * sizeof(double)))
+    return P3M_EINVAL;
+  return status_of(launch_drift_vjp(n, mom_bar, pos_bar, mass, mass_scalar, c_drift,
+                                    (hipStream_t)hip_stream));
 }
 
 int p3m_set_timing(p3m_plan* P, int32_t capacity) {

@@ -51,6 +51,10 @@ struct Workspace {
   void* gtab = nullptr;         // [2*ng]    Green's function factor tables (T)
   unsigned long long* counter = nullptr;  // [1] pair-count scratch
   float* split_tab = nullptr;   // [4][kSplitBins + 1] cubic pieces of f(r) on [0, r_c)
+  // adjoint workspace (plans created with params.adjoint != 0)
+  void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
+  void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
+  void* lam_grid = nullptr;     // [3][ng^3] CIC deposit of m * cotangent
 };
 
 }  // namespace p3m
@@ -107,6 +111,18 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
 template <typename T>
 hipError_t launch_tables(p3m_plan* P);
 
+// Adjoint stages (workspace of plans created with params.adjoint != 0).
+template <typename T>
+hipError_t launch_lambda_sort(p3m_plan* P, int64_t n, const double* force_bar);
+template <typename T>
+hipError_t launch_deposit_lambda(p3m_plan* P);   // divergence of the deposit -> grid2
+template <typename T>
+hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar);
+template <typename T>
+hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar,
+                            bool uniform_mass);
+hipError_t launch_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar,
+                            const double* mass, double ms, double c, hipStream_t s);
 hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,
                        hipStream_t s);
 hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double* mass,

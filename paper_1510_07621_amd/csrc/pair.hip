@@ -64,6 +64,10 @@ struct PairArgs {
   const float* __restrict__ split_tab;  // [4][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
   double wscale;                        // -G, times s^3 on the FP32 path
+  // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
+  // pair Hessian (see pair_vjp_weights)
+  const typename Vec<T>::v4* __restrict__ lam;
+  T vjp_ce, vjp_k5, vjp_e2;
   const typename Vec<T>::v4* __restrict__ acc_pm;  // sorted PM acceleration or null
   const int32_t* __restrict__ perm;
   int64_t n;
@@ -108,6 +112,43 @@ __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>&
   return r2 > 0.0 ? f * (inv * inv * inv) : 0.0;   // eps may be 0
 }
 
+// Adjoint weights of a pair: with g = f / rho^3 and the pair Jacobian
+// J = g I + (g'(r)/r) r r^T, J dl = w1 dl + w2 (r . dl) r, where
+// w1 = g and w2 = g'(r)/r = -(r e^{-u^2} / (2 sqrt(pi) r_s^3)) / rho^3 - 3 f / rho^5,
+// both (FP32) in the scaled units of pair_weight: rsq(q) = 1 / (s rho), the
+// common factor s^3 folded into wscale, vjp_k5 = 3 s^2; FP64: s = 1.
+template <int TAB>
+__device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>& A,
+                                                 const SplitTable& tab, float& w1, float& w2) {
+  const float q = __builtin_fmaf(r2, A.tab_s2, A.tab_e2);
+  const float inv = __builtin_amdgcn_rsqf(q);
+  const float x = TAB ? __builtin_fmaf(q, inv, -A.tab_off)
+                      : __builtin_amdgcn_sqrtf(r2) * A.tab_s;
+  const int k = (int)x;
+  const float t = __builtin_amdgcn_fractf(x);
+  const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
+  const float inv3 = inv * inv * inv;
+  const float re = __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_exp2f(r2 * A.vjp_e2);
+  const bool pos = r2 > 0.f;            // self pairs: zero, never inf * 0
+  w1 = pos ? f * inv3 : 0.f;
+  w2 = pos ? -inv3 * (A.vjp_ce * re + A.vjp_k5 * f * (inv * inv)) : 0.f;
+}
+
+template <int TAB>
+__device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<double>& A,
+                                                 const SplitTable&, double& w1, double& w2) {
+  const double kTwoOverSqrtPi = 1.1283791670955126;
+  const double inv = rsqrt(r2 + A.eps2);
+  const double r = sqrt(r2);
+  const double u = r * A.inv2rs;
+  const double e = exp(-u * u);
+  const double f = erfc(u) + kTwoOverSqrtPi * u * e;
+  const double inv3 = inv * inv * inv;
+  const bool pos = r2 > 0.0;                      // eps may be 0
+  w1 = pos ? f * inv3 : 0.0;
+  w2 = pos ? -inv3 * (A.vjp_ce * r * e + A.vjp_k5 * f * (inv * inv)) : 0.0;
+}
+
 __device__ __forceinline__ int wave_inclusive(int v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -118,11 +159,12 @@ __device__ __forceinline__ int wave_inclusive(int v) {
   return v;
 }
 
-template <typename T>
+template <typename T, bool VJP>
 struct PairShared {
   SplitTable tab;                          // FP32 path only; first, so one address
                                            // register reaches all four arrays
   typename Vec<T>::v4 jb[kPairCap + 64];   // staged j (+ far sentinels); reused for the reduction
+  typename Vec<T>::v4 jl[VJP ? kPairCap + 64 : 1];   // adjoint mode: staged j cotangents
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
   int owner[kPairCap];                     // run of each staged entry of a chunk
   T d_sx[64], d_sy[64];
@@ -171,9 +213,10 @@ __device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, int rb,
 }
 
 // One work item with U i-slots per lane. UM: every particle has the same mass
-// (mass applied once at the end instead of per pair).
-template <typename T, int U, bool COUNT, bool UM, int TAB>
-__device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S, int gx0,
+// (mass applied once at the end instead of per pair). VJP: the adjoint sum
+// J(r_ij) (lam_i - lam_j) in place of the force r_ij g(r_ij).
+template <typename T, int U, bool COUNT, bool UM, int TAB, bool VJP>
+__device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJP>& S, int gx0,
                                           int gy0, int gz0, int ibeg, int ni) {
   using T4 = typename Vec<T>::v4;
   const int lane = threadIdx.x;
@@ -185,6 +228,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
   const bool active = st < ns;
 
   T xi[U], yi[U], zi[U], ax[U], ay[U], az[U];
+  T lxi[VJP ? U : 1], lyi[VJP ? U : 1], lzi[VJP ? U : 1];
   int si[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -200,6 +244,12 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
     yi[u] = has ? T(run & (G - 1)) * h + pi.y : T(kFar);
     zi[u] = has ? T(czi - gz0) * h + pi.z : T(kFar);
     ax[u] = ay[u] = az[u] = T(0);
+    if constexpr (VJP) {
+      const T4 li = A.lam[si[u]];
+      lxi[u] = li.x;
+      lyi[u] = li.y;
+      lzi[u] = li.z;
+    }
   }
   int npairs = 0;
 
@@ -275,13 +325,14 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
           const int f = c0 + q0 + e;
           src[e] = q0 + e < cn ? S.d_lo[dd[e]] + (f - S.d_pre[dd[e]]) : -1;
         }
-        T4 pj[kStage];
+        T4 pj[kStage], lj[VJP ? kStage : 1];
         int cz[kStage];
 #pragma unroll
         for (int e = 0; e < kStage; ++e) {
           if (src[e] >= 0) {
             pj[e] = A.rec[src[e]];
             cz[e] = A.skey[src[e]] & mask;
+            if constexpr (VJP) lj[e] = A.lam[src[e]];
           }
         }
 #pragma unroll
@@ -294,6 +345,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
             o.z = T(cz[e] + S.d_zs[d]) * h + pj[e].z;
             o.w = pj[e].w;
             S.jb[q0 + e] = o;
+            if constexpr (VJP) S.jl[q0 + e] = lj[e];
           }
         }
       }
@@ -311,6 +363,34 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
       // sentinels, and empty slots sit at +kFar, so both fail the cutoff test
       const int iters = (cn + ns - 1) / ns;
       const T4* jp = S.jb + st;
+      if constexpr (VJP) {
+        // sentinel slots carry no cotangent; their separations fail the test
+        const T4* lp = S.jl + st;
+#pragma unroll 2
+        for (int t = 0; t < iters; ++t) {
+          const T4& pj = jp[t * ns];
+          const T4 lj = t * ns + st < cn ? lp[t * ns] : T4{};
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const T dx = xi[u] - pj.x, dy = yi[u] - pj.y, dz = zi[u] - pj.z;
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < A.rc2) {
+              T w1, w2;
+              pair_vjp_weights<TAB>(r2, A, S.tab, w1, w2);
+              const T lx = lxi[u] - lj.x, ly = lyi[u] - lj.y, lz = lzi[u] - lj.z;
+              T c = w2 * (dx * lx + dy * ly + dz * lz);
+              if (!UM) {
+                w1 *= pj.w;
+                c *= pj.w;
+              }
+              ax[u] += w1 * lx + c * dx;
+              ay[u] += w1 * ly + c * dy;
+              az[u] += w1 * lz + c * dz;
+            }
+          }
+        }
+        continue;
+      }
 #pragma unroll 2
       for (int t = 0; t < iters; ++t) {
         const T4& pj = jp[t * ns];
@@ -391,10 +471,10 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T>& S
   }
 }
 
-template <typename T, bool COUNT, bool UM, int TAB>
+template <typename T, bool COUNT, bool UM, int TAB, bool VJP = false>
 __global__ void __launch_bounds__(64)
 k_pairs(PairArgs<T> A) {
-  __shared__ PairShared<T> S;
+  __shared__ PairShared<T, VJP> S;
   const int lane = threadIdx.x;
   // Items in group order, dealt round-robin over the XCDs by the hardware:
   // the eight XCDs then work on neighbouring groups at the same time, which
@@ -433,13 +513,13 @@ k_pairs(PairArgs<T> A) {
   const int ni = min(kChunk, ntot - ibeg);
   // i-slots per lane: enough that ceil(ni / U) slot sets fit in the wave
   if (ni == 1)
-    pair_item<T, 1, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 1, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
   else if (sizeof(T) == 8)
-    pair_item<T, 2, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
-  else if (ni <= 64)
-    pair_item<T, 4, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 2, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
+  else if (ni <= 64 || VJP)
+    pair_item<T, 4, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
   else
-    pair_item<T, 8, COUNT, UM, TAB>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_item<T, 8, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
 }
 
 // Grid of the pair kernel: the item bound rounded up to a multiple of kXcds.
@@ -475,7 +555,12 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.tab_e2 = (float)std::max(s * s * P->eps * P->eps, 1e-12);
     A.tab_off = (float)(s * P->tab_v0);
     A.wscale *= s * s * s;
+    A.vjp_k5 = (T)(3.0 * s * s);
+    A.vjp_e2 = (T)(-1.4426950408889634 / (4.0 * P->r_s * P->r_s));
+  } else {
+    A.vjp_k5 = T(3);
   }
+  A.vjp_ce = (T)(1.0 / (2.0 * 1.7724538509055160 * P->r_s * P->r_s * P->r_s));
   A.perm = W.perm;
   A.n = n;
   return A;
@@ -508,6 +593,31 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
 }
 
 template <typename T>
+hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar,
+                            bool uniform_mass) {
+  PairArgs<T> A = make_args<T>(P, n);
+  A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
+  A.lam = (const typename Vec<T>::v4*)P->ws.lam;
+  A.force = pos_bar;
+  A.force_fp32 = 0;
+  const unsigned grid = pair_grid(P);
+  if constexpr (sizeof(T) == 4) {
+    if (P->tab_var == 1) {
+      if (uniform_mass)
+        k_pairs<T, false, true, 1, true><<<grid, 64, 0, P->stream>>>(A);
+      else
+        k_pairs<T, false, false, 1, true><<<grid, 64, 0, P->stream>>>(A);
+      return hipGetLastError();
+    }
+  }
+  if (uniform_mass)
+    k_pairs<T, false, true, 0, true><<<grid, 64, 0, P->stream>>>(A);
+  else
+    k_pairs<T, false, false, 0, true><<<grid, 64, 0, P->stream>>>(A);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
   PairArgs<T> A = make_args<T>(P, n);
   A.counter = (unsigned long long*)count_out;
@@ -519,6 +629,8 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
 
 template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int, bool);
 template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, bool);
+template hipError_t launch_pairs_vjp<float>(p3m_plan*, int64_t, bool, double*, bool);
+template hipError_t launch_pairs_vjp<double>(p3m_plan*, int64_t, bool, double*, bool);
 template hipError_t launch_pair_count<float>(p3m_plan*, int64_t, int64_t*);
 template hipError_t launch_pair_count<double>(p3m_plan*, int64_t, int64_t*);
 

@@ -76,6 +76,10 @@ def test_plan_create_rejects_bad_sizes_and_nulls(b):
     bad = b.Params(grid_n=32, precision="fp32").to_c()
     bad.precision = 7
     assert b._lib.p3m_plan_create(ctypes.byref(bad), 4, None, ctypes.byref(h)) == -1
+    bad = b.Params(grid_n=32, adjoint=True).to_c()
+    assert bad.adjoint == 1
+    bad.adjoint = 2
+    assert b._lib.p3m_plan_create(ctypes.byref(bad), 4, None, ctypes.byref(h)) == -1
 
 
 def test_calls_on_null_plan_and_bad_arguments(b):
@@ -94,6 +98,14 @@ def test_calls_on_null_plan_and_bad_arguments(b):
     assert L.p3m_drift(0, None, None, None, 1.0, 1.0, 1.0, None) == 0
     assert L.p3m_drift(5, 1, 1, None, 1.0, 1.0, 0.0, None) == -1     # box <= 0
     assert L.p3m_drift(5, 1, 1, None, 0.0, 1.0, 1.0, None) == -1     # zero scalar mass
+    for fn in (L.p3m_force_vjp, L.pm_force_vjp, L.pp_force_vjp):
+        assert fn(None, 10, 1, None, 1.0, 2, 3) == -1
+    assert L.p3m_drift_vjp(-1, 1, 2, None, 1.0, 1.0, None) == -1
+    assert L.p3m_drift_vjp(0, None, None, None, 1.0, 1.0, None) == 0    # empty: no-op
+    assert L.p3m_drift_vjp(5, None, 2, None, 1.0, 1.0, None) == -1
+    assert L.p3m_drift_vjp(5, 1, 4096, None, 0.0, 1.0, None) == -1     # zero scalar mass
+    assert L.p3m_drift_vjp(5, 4096, 4096, None, 1.0, 1.0, None) == -1  # in place on itself
+    assert L.p3m_drift_vjp(5, 4096, 8192, None, 1.0, float("inf"), None) == -1
     st = b._lib.p3m_stencil_rows(0, 5.0, None, 0)
     assert st == -1
 

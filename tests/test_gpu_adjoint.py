@@ -1,0 +1,187 @@
+"""GPU parity of the force adjoint and the differentiable leapfrog.
+
+The HIP path through the C ABI (p3m_force_vjp, pm_force_vjp, pp_force_vjp,
+p3m_drift_vjp) against the oracle's transposes (oracle.adjoint), which are
+pinned by finite differences on the CPU. Tolerances (per-particle relative
+error of pos_bar, RMS): FP64 1e-9, FP32 1e-4; the drift transpose bit for
+bit. Also: the GPU's own finite differences (<mu, VJP(lam)> = <lam, JVP(mu)>
+with FP64 forces), conservation invariants, and torch.autograd through
+autodiff.force and autodiff.leapfrog (with and without checkpointing).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint, metrics
+from paper_1510_07621_amd import ics
+
+from _gpu import dev, host, plan, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _err(got, ref):
+    return metrics.force_errors(got, ref)["rms"]
+
+
+GRID = 16
+H = 1.0 / GRID
+EPS = 0.03 * H
+KW = dict(rs_cells=1.25, cutoff_rs=4.5, eps=EPS, G=1.0)
+
+
+@pytest.fixture(scope="module")
+def case():
+    """4096 particles on a 16^3 grid (one per cell on average) plus 200 close
+    companions; per-particle masses; a random cotangent."""
+    rng = np.random.default_rng(41)
+    base = ics.uniform(4096, seed=42)
+    near = (base[:, :200] + rng.uniform(0.05, 0.3, (3, 200)) * H) % 1.0
+    pos = np.concatenate([base, near], axis=1)
+    n = pos.shape[1]
+    m = rng.uniform(0.5, 1.5, n) / n
+    lam = rng.normal(size=(3, n))
+    r_s = 1.25 * H
+    r_c = 4.5 * r_s
+    pp = adjoint.pp_vjp(pos, m, 1.0, r_s, r_c, EPS, lam)
+    pm = adjoint.pm_vjp(pos, m, 1.0, GRID, r_s, lam)
+    return pos, m, lam, pp, pm
+
+
+def _vjp_plan(n, precision, **kw):
+    return plan(GRID, n, precision, softening=EPS, adjoint=True, **kw)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_force_vjp_parity(case, precision, tol):
+    pos, m, lam, pp, pm = case
+    with _vjp_plan(pos.shape[1], precision) as P:
+        x, mm, l = dev(pos), dev(m), dev(lam)
+        got_pp = host(P.pp_force_vjp(x, mm, l))
+        got_pm = host(P.pm_force_vjp(x, mm, l))
+        got = host(P.force_vjp(x, mm, l))
+    assert _err(got_pp, pp) <= tol
+    assert _err(got_pm, pm) <= tol
+    assert _err(got, pp + pm) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_force_vjp_uniform_mass_and_invariants(case, precision):
+    """Scalar mass (the per-pair mass factor folded out), and conservation:
+    a uniform cotangent has a zero adjoint (total momentum is conserved by
+    both force parts)."""
+    pos, _, lam, _, _ = case
+    n = pos.shape[1]
+    ms = 1.0 / n
+    ref = adjoint.p3m_vjp(pos, ms, 1.0, GRID, lam, 1.25, 4.5, EPS)
+    with _vjp_plan(n, precision) as P:
+        x = dev(pos)
+        got = host(P.force_vjp(x, ms, dev(lam)))
+        uni = np.tile(np.array([[0.7], [-0.2], [1.1]]), (1, n))
+        zero = host(P.force_vjp(x, ms, dev(uni)))
+    assert _err(got, ref) <= (1e-9 if precision == "fp64" else 1e-4)
+    scale = np.sqrt(np.mean(np.sum(ref * ref, axis=0)))
+    assert np.sqrt(np.mean(np.sum(zero * zero, axis=0))) <= (1e-9 if precision == "fp64"
+                                                             else 1e-4) * scale
+
+
+def test_force_vjp_matches_gpu_finite_differences(case):
+    """<mu, VJP(lam)> against <lam, (F(x + d mu) - F(x - d mu)) / 2d> with the
+    GPU's FP64 force: the adjoint is the transpose of the force it ships with."""
+    pos, m, lam, _, _ = case
+    rng = np.random.default_rng(43)
+    mu = rng.normal(size=pos.shape)
+    d = 1e-7 * H
+    with _vjp_plan(pos.shape[1], "fp64") as P:
+        mm = dev(m)
+        vjp = host(P.force_vjp(dev(pos), mm, dev(lam)))
+        fp = host(P.force(dev((pos + d * mu) % 1.0), mm))
+        fm = host(P.force(dev((pos - d * mu) % 1.0), mm))
+    lhs = np.sum(mu * vjp)
+    rhs = np.sum(lam * (fp - fm)) / (2 * d)
+    # pairs crossing r_c or particles crossing node planes within d are rare
+    # and each moves the finite difference by a bounded jump
+    assert abs(lhs - rhs) <= 1e-4 * np.sum(np.abs(mu * vjp))
+
+
+def test_drift_vjp_bitwise():
+    from paper_1510_07621_amd import binding
+    rng = np.random.default_rng(44)
+    n = 10007
+    xb, pb = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+    m = rng.uniform(0.5, 2.0, n)
+    dt = 0.0137
+    for mass in (m, 0.37):
+        zero_vjp = lambda x, l: np.zeros_like(l)
+        _, ref = adjoint.leapfrog_vjp([xb, xb], mass, zero_vjp, dt, xb, pb)
+        p = dev(pb)
+        binding.drift_vjp(p, dev(xb), dev(mass) if isinstance(mass, np.ndarray) else mass, dt)
+        np.testing.assert_array_equal(host(p), ref)
+
+
+def test_vjp_needs_an_adjoint_plan_and_checks_arguments():
+    from paper_1510_07621_amd import binding
+    pos = dev(ics.uniform(100, seed=45))
+    lam = torch.zeros_like(pos)
+    with plan(GRID, 100, "fp64") as P:
+        with pytest.raises(ValueError):
+            P.force_vjp(pos, 0.01, lam)
+    with _vjp_plan(100, "fp64") as P:
+        with pytest.raises(ValueError):
+            P.force_vjp(pos, 0.01, lam, out=pos)            # overlaps pos
+        with pytest.raises(ValueError):
+            P.force_vjp(pos, 0.01, lam[:, :50].contiguous())
+        empty = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+        assert P.force_vjp(empty, 0.01, empty).shape == (3, 0)
+    with pytest.raises(ValueError):
+        binding.drift_vjp(lam, lam, 1.0, 0.1)               # in place on itself
+
+
+def test_autograd_force_matches_force_vjp(case):
+    from paper_1510_07621_amd import autodiff
+    pos, m, lam, pp, pm = case
+    with _vjp_plan(pos.shape[1], "fp64") as P:
+        x = dev(pos).requires_grad_(True)
+        F = autodiff.force(P, x, dev(m))
+        (g,) = torch.autograd.grad((F * dev(lam)).sum(), x)
+    assert _err(host(g), pp + pm) <= 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+@pytest.mark.parametrize("segment", [None, 1, 6])
+def test_leapfrog_gradient_matches_the_oracle(precision, tol, segment):
+    """6 KDK steps (dt = 0.02) of 1000 particles on a 16^3 grid from small
+    random momenta: torch.autograd through autodiff.leapfrog against the
+    oracle's transposed trajectory (oracle forward, oracle adjoint), for
+    checkpoint segments of ceil(sqrt(6)) = 3 steps, 1 (every state kept) and
+    6 (one checkpoint)."""
+    from oracle.p3m import p3m_accel
+    from paper_1510_07621_amd import autodiff
+    rng = np.random.default_rng(46)
+    n, steps, dt = 1000, 6, 0.02
+    pos = ics.uniform(n, seed=47)
+    mom = rng.normal(size=(3, n)) * 1e-4
+    ms = 1.0 / n
+    xb, pb = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+
+    def force(x):
+        return ms * p3m_accel(x, ms, 1.0, GRID, 1.25, 4.5, EPS)
+
+    vjp_fn = lambda x, l: adjoint.p3m_vjp(x, ms, 1.0, GRID, l, **KW)
+    xs, pT = adjoint.leapfrog(pos, mom, ms, force, dt, 1.0, steps)
+    x0b, p0b = adjoint.leapfrog_vjp(xs, ms, vjp_fn, dt, xb, pb)
+
+    with _vjp_plan(n, precision) as P:
+        x0 = dev(pos).requires_grad_(True)
+        p0 = dev(mom).requires_grad_(True)
+        xT, pT_gpu = autodiff.leapfrog(P, x0, p0, ms, dt, 1.0, steps, segment)
+        loss = (xT * dev(xb)).sum() + (pT_gpu * dev(pb)).sum()
+        gx, gp = torch.autograd.grad(loss, (x0, p0))
+    assert _err(host(xT), xs[-1]) <= 1e-12 * 10 ** (6 if precision == "fp32" else 0)
+    assert _err(host(gx), x0b) <= tol
+    assert _err(host(gp), p0b) <= tol
