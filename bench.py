@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 step timing")
     ap.add_argument("--cpu-sample", type=int, default=20000,
                     help="particles whose short-range force the CPU oracle evaluates")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward timing of the differentiable leapfrog")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a plain copy "
                          "of known size, to scale memory counters in a profiled run)")
@@ -109,6 +111,49 @@ def time_precision(binding, torch, w, pos0, precision, steps, warmup, dt):
         "pairs": 0.5 * (pairs_before + pairs_after),
         "pairs_before": pairs_before, "pairs_after": pairs_after,
     }
+
+
+def adjoint_leg(binding, torch, name, precision, segment=None, keep_grad=False):
+    """Forward and backward time of the differentiable leapfrog: the
+    workload's KDK steps from its positions at rest, loss = sum of squared
+    final displacements (minimum image, from the initial positions), gradient
+    with respect to the initial positions through autodiff.leapfrog with
+    checkpoints every `segment` steps (default ceil(sqrt(steps))). One
+    untimed warm-up pass."""
+    import math
+    from paper_1510_07621_amd import autodiff, ics
+    w = ics.workload(name)
+    x0 = torch.as_tensor(w.positions(), device="cuda").contiguous()
+    p0 = torch.zeros_like(x0)
+    seg = segment or max(1, math.ceil(math.sqrt(w.steps)))
+    P = binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
+                                    cutoff_rs=w.cutoff_rs, softening=w.softening, G=w.G,
+                                    precision=precision, adjoint=True), w.n)
+
+    def run():
+        x = x0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xT, _ = autodiff.leapfrog(P, x, p0, w.mass, w.dt, w.box, w.steps, seg)
+        d = xT - x0
+        d = d - w.box * torch.round(d / w.box)
+        loss = (d * d).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (g,) = torch.autograd.grad(loss, x)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, float(loss.detach()), g
+
+    run()
+    tf, tb, loss, g = run()
+    P.close()
+    if keep_grad:
+        return g
+    return {"workload": name, "n_particles": w.n, "grid_n": w.grid_n, "steps": w.steps,
+            "dt": w.dt, "precision": precision, "checkpoint_segment": seg,
+            "forward_s": tf, "backward_s": tb, "ratio": tb / tf, "loss": loss,
+            "grad_rms": float(torch.sqrt((g * g).sum(0).mean()))}
 
 
 def cpu_leg(binding, torch, w, pos, n_sample):
@@ -215,6 +260,22 @@ def main():
             "pp_frac_of_fp64_peak": r64["pairs"] * FLOP_PER_PAIR / (pp64 * 1e-3) / 1e12
                                     / FP64_PEAK_TFLOPS,
         }
+    if not args.no_adjoint:
+        legs = [adjoint_leg(binding, torch, "zeldovich64_kdk", "fp64", segment=1),
+                adjoint_leg(binding, torch, "plummer128_kdk", "fp32")]
+        out["adjoint_fwd_ratio"] = {leg["workload"]: leg["ratio"] for leg in legs}
+        out["adjoint"] = legs
+        # FP32-pair gradient of the clustered run against the FP64 path's, on
+        # a 16^3 subset of particles (per-particle relative error of dL/dx0)
+        g32 = adjoint_leg(binding, torch, "plummer128_kdk", "fp32", keep_grad=True)
+        g64 = adjoint_leg(binding, torch, "plummer128_kdk", "fp64", keep_grad=True)
+        sub = np.random.default_rng(16).choice(g64.shape[1], size=16 ** 3, replace=False)
+        a = g32[:, sub].cpu().numpy()
+        b = g64[:, sub].cpu().numpy()
+        rel = np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+        legs[1]["grad_err_vs_fp64_subset"] = {"rms": float(np.sqrt(np.mean(rel ** 2))),
+                                              "median": float(np.median(rel)),
+                                              "max": float(rel.max()), "particles": 16 ** 3}
     if not args.no_cpu:
         base, errs = cpu_leg(binding, torch, w, pos, args.cpu_sample)
         out["cpu_baseline"] = base

@@ -204,9 +204,11 @@ WORKLOADS = {
     # 64^3 Zel'dovich ICs, 64^3 grid, 10 leapfrog steps of dt = 0.01.
     "zeldovich64_kdk": Workload("zeldovich64_kdk", 64, 64, "zeldovich", seed=4,
                                 steps=10, dt=0.01),
-    # 128^3 Plummer mix, 128^3 grid, 50 leapfrog steps.
+    # 128^3 Plummer mix, 128^3 grid, 50 leapfrog steps of dt = 0.001: the
+    # smallest spheres (a = 0.002 box, ~734 particles) have a dynamical time
+    # sqrt(a^3 / (G M)) ~ 5e-3, which a step of 0.01 would not resolve.
     "plummer128_kdk": Workload("plummer128_kdk", 128, 128, "plummer", seed=5,
-                               steps=50, dt=0.01),
+                               steps=50, dt=0.001),
 }
 
 
