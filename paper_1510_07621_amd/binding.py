@@ -73,6 +73,7 @@ def _load():
         "p3m_group_edge": (i32, [i64, i32]),
         "p3m_split_table": (i32, [dbl, dbl, ctypes.POINTER(ctypes.c_float), i32,
                                   ctypes.POINTER(dbl)]),
+        "p3m_split_table64": (i32, [dbl, ctypes.POINTER(dbl), i32]),
         "p3m_cosmo_age": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
                                          ctypes.POINTER(dbl)]),
         "p3m_cosmo_scale_factor": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
@@ -156,6 +157,17 @@ def split_table(cutoff_rs: float, softening_rs: float = 0.0):
            "p3m_split_table")
     tab = np.frombuffer(buf, dtype=np.float32).reshape(4, b + 1).copy()
     return tab, (int(m[0]), float(m[1]), float(m[2]))
+
+
+def split_table64(cutoff_rs: float):
+    """FP64 split-factor table of the pair sum: an (8, B + 1) float64 array,
+    row l the coefficient of tau^l of each bin of r in [0, r_c)."""
+    import numpy as np
+    b = _lib.p3m_split_table64(cutoff_rs, None, 0)
+    _check(min(b, 0), "p3m_split_table64")
+    buf = (ctypes.c_double * (8 * (b + 1)))()
+    _check(min(_lib.p3m_split_table64(cutoff_rs, buf, 8 * (b + 1)), 0), "p3m_split_table64")
+    return np.frombuffer(buf, dtype=np.float64).reshape(8, b + 1).copy()
 
 
 @dataclass(frozen=True)

@@ -43,7 +43,7 @@ void free_workspace(p3m_plan* P) {
   Workspace& W = P->ws;
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
-                  W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.lam,
+                  W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.split_tab64, W.lam,
                   W.grid2, W.lam_grid};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -285,6 +285,42 @@ SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out) {
   return m;
 }
 
+void split_table64(double cutoff_rs, double* out) {
+  // Piece k covers u = (k + t) u_c / B, t in [0, 1]; with tau = 2t - 1 the
+  // degree-7 polynomial through f at the eight Chebyshev points of [-1, 1],
+  // solved in extended precision so that only the final rounding to double
+  // remains (the pieces are narrow, so the coefficients fall off fast).
+  typedef long double LD;
+  const int B = kSplitBins, C = kSplitCoef64, stride = B + 1;
+  const LD kPi = 3.14159265358979323846264338327950288L;
+  const LD u_c = 0.5L * (LD)cutoff_rs;
+  auto f = [](LD u) { return std::erfc(u) + 1.12837916709551257389615890312154517L * u *
+                                                std::exp(-u * u); };
+  for (int k = 0; k < B; ++k) {
+    LD V[kSplitCoef64][kSplitCoef64 + 1];
+    for (int j = 0; j < C; ++j) {
+      LD tau = std::cos((2 * j + 1) * kPi / (2 * C));
+      LD p = 1.0L;
+      for (int l = 0; l < C; ++l, p *= tau) V[j][l] = p;
+      V[j][C] = f(u_c * ((LD)k + 0.5L * (tau + 1.0L)) / B);
+    }
+    for (int col = 0; col < C; ++col) {     // Gauss-Jordan, partial pivoting
+      int piv = col;
+      for (int r = col + 1; r < C; ++r)
+        if (std::fabs(V[r][col]) > std::fabs(V[piv][col])) piv = r;
+      for (int l = 0; l <= C; ++l) std::swap(V[col][l], V[piv][l]);
+      for (int r = 0; r < C; ++r) {
+        if (r == col) continue;
+        LD m = V[r][col] / V[col][col];
+        for (int l = col; l <= C; ++l) V[r][l] -= m * V[col][l];
+      }
+    }
+    for (int l = 0; l < C; ++l) out[l * stride + k] = (double)(V[l][C] / V[l][l]);
+  }
+  out[B] = (double)f(u_c);
+  for (int l = 1; l < C; ++l) out[l * stride + B] = 0.0;
+}
+
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
   if (g < 1 || !(radius_cells > 0) || !std::isfinite(radius_cells)) return P3M_EINVAL;
   // A cell can hold a partner closer than r_c iff its gap to the group box is
@@ -341,6 +377,13 @@ int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32
       map_out[2] = m.v1;
     }
   }
+  return kSplitBins;
+}
+
+int32_t p3m_split_table64(double cutoff_rs, double* out, int32_t cap) {
+  if (!(cutoff_rs > 0) || !std::isfinite(cutoff_rs) || cap < 0 || (cap > 0 && !out))
+    return P3M_EINVAL;
+  if (cap >= kSplitCoef64 * (kSplitBins + 1)) p3m::split_table64(cutoff_rs, out);
   return kSplitBins;
 }
 
@@ -438,6 +481,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   W.gtab = dev_alloc<unsigned char>(2 * q.grid_n * real, err);
   W.counter = dev_alloc<unsigned long long>(1, err);
   W.split_tab = dev_alloc<float>(4 * (kSplitBins + 1), err);
+  W.split_tab64 = dev_alloc<double>(kSplitCoef64 * (kSplitBins + 1), err);
   if (q.adjoint) {
     W.lam = dev_alloc<unsigned char>(nn * 4 * real, err);
     W.grid2 = dev_alloc<unsigned char>(P->ncell * real, err);
@@ -461,6 +505,11 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
     P->tab_v0 = m.v0 * r_s;
     P->tab_v1 = m.v1 * r_s;
     err = hipMemcpy(W.split_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
+  }
+  if (err == hipSuccess) {
+    double tab64[kSplitCoef64 * (kSplitBins + 1)];
+    split_table64(q.cutoff_rs, tab64);
+    err = hipMemcpy(W.split_tab64, tab64, sizeof(tab64), hipMemcpyHostToDevice);
   }
   if (err == hipSuccess)
     err = q.precision == P3M_FP32 ? launch_tables<float>(P) : launch_tables<double>(P);

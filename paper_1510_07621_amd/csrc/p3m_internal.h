@@ -25,7 +25,8 @@ constexpr int kPairCap = 256;     // j-particles staged in LDS per pass of the p
 constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
 constexpr int kChunk = 128;       // i-particles per pair-loop work item (one wavefront)
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
-constexpr int kSplitBins = 64;    // cubic pieces of the FP32 split-factor table
+constexpr int kSplitBins = 64;    // pieces of the split-factor tables
+constexpr int kSplitCoef64 = 8;   // coefficients per piece of the FP64 table (degree 7)
 constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
 
 // One particle in cell order: offsets from its cell's lower corner and mass.
@@ -50,7 +51,8 @@ struct Workspace {
   void* twiddle = nullptr;      // [ng/2]    exp(-2 pi i k / ng) (T2)
   void* gtab = nullptr;         // [2*ng]    Green's function factor tables (T)
   unsigned long long* counter = nullptr;  // [1] pair-count scratch
-  float* split_tab = nullptr;   // [4][kSplitBins + 1] cubic pieces of f(r) on [0, r_c)
+  float* split_tab = nullptr;   // [4][kSplitBins + 1] cubic pieces of f on [0, r_c)
+  double* split_tab64 = nullptr;  // [kSplitCoef64][kSplitBins + 1] FP64 pieces of f(r)
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
   void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
@@ -138,5 +140,8 @@ struct SplitMap {
   double v0, v1;
 };
 SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out);
+// FP64 table over r in [0, r_c): out[l * (kSplitBins + 1) + k] is the
+// coefficient of tau^l (tau = 2t - 1) of piece k; entry kSplitBins = f(r_c).
+void split_table64(double cutoff_rs, double* out);
 
 }  // namespace p3m

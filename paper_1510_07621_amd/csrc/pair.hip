@@ -31,7 +31,9 @@
 // sqrt(r^2 + eps^2), which rsq already yields, so a pair costs a single
 // transcendental; when eps is too large against a piece for the cubic to
 // follow the kink at r = 0, the plan tabulates over r and a square root is
-// added. FP64: the device library's erfc, exp, sqrt and rsqrt.
+// added. FP64: the device library's sqrt and rsqrt, and f from 64 pieces of
+// degree 7 over r in [0, r_c) (fitted in extended precision at the Chebyshev
+// points of each piece; error at FP64 rounding).
 #include <algorithm>
 
 #include "p3m_internal.h"
@@ -61,8 +63,9 @@ struct PairArgs {
   // length, q = s^2 (r^2 + eps^2), the bin coordinate is x = q rsq(q) - s v0
   // (softened variable) or x = s r (plain r), and the returned weight is
   // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
-  const float* __restrict__ split_tab;  // [4][kSplitBins + 1]
+  const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
+  double tab_s64;                       // FP64 table: kSplitBins / r_c
   double wscale;                        // -G, times s^3 on the FP32 path
   // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
   // pair Hessian (see pair_vjp_weights)
@@ -76,12 +79,31 @@ struct PairArgs {
   unsigned long long* __restrict__ counter;      // pair count mode
 };
 
-// The FP32 split-factor table in LDS: four coefficient arrays, so that the
-// random per-lane bin lookups spread over the banks.
+// The split-factor table in LDS, one array per coefficient so that the
+// random per-lane bin lookups spread over the banks. FP32: cubic pieces in
+// t in [0, 1); FP64: degree-7 pieces in tau = 2t - 1 in [-1, 1).
 constexpr int kTabStride = kSplitBins + 1;
-struct SplitTable {
-  float c[4][kTabStride];
+template <typename T> struct SplitTable;
+template <> struct SplitTable<float> {
+  static constexpr int kCoef = 4;
+  float c[kCoef][kTabStride];
 };
+template <> struct SplitTable<double> {
+  static constexpr int kCoef = kSplitCoef64;
+  double c[kCoef][kTabStride];
+};
+
+// FP64 split factor f(r) from the table over x = r kSplitBins / r_c.
+__device__ __forceinline__ double split_f64(double r2, const PairArgs<double>& A,
+                                            const SplitTable<double>& tab) {
+  const double x = sqrt(r2) * A.tab_s64;
+  const int k = (int)x;                 // <= kSplitBins since r < r_c
+  const double tau = 2.0 * (x - (double)k) - 1.0;
+  double f = tab.c[kSplitCoef64 - 1][k];
+#pragma unroll
+  for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * tau + tab.c[l][k];
+  return f;
+}
 
 // f(r) / (r^2 + eps^2)^(3/2) for 0 <= r < r_c, up to the factor folded into
 // wscale. Self pairs (r = 0) give a finite weight times a zero separation.
@@ -91,7 +113,7 @@ struct SplitTable {
 // weight finite at r = 0 when eps = 0.
 template <int TAB>
 __device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
-                                             const SplitTable& tab) {
+                                             const SplitTable<float>& tab) {
   const float q = __builtin_fmaf(r2, A.tab_s2, A.tab_e2);
   const float inv = __builtin_amdgcn_rsqf(q);
   const float x = TAB ? __builtin_fmaf(q, inv, -A.tab_off)
@@ -104,11 +126,9 @@ __device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
 
 template <int TAB>
 __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>& A,
-                                              const SplitTable&) {
-  const double kTwoOverSqrtPi = 1.1283791670955126;
-  double inv = rsqrt(r2 + A.eps2);
-  double u = sqrt(r2) * A.inv2rs;
-  double f = erfc(u) + kTwoOverSqrtPi * u * exp(-u * u);
+                                              const SplitTable<double>& tab) {
+  const double inv = rsqrt(r2 + A.eps2);
+  const double f = split_f64(r2, A, tab);
   return r2 > 0.0 ? f * (inv * inv * inv) : 0.0;   // eps may be 0
 }
 
@@ -119,7 +139,8 @@ __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>&
 // common factor s^3 folded into wscale, vjp_k5 = 3 s^2; FP64: s = 1.
 template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>& A,
-                                                 const SplitTable& tab, float& w1, float& w2) {
+                                                 const SplitTable<float>& tab, float& w1,
+                                                 float& w2) {
   const float q = __builtin_fmaf(r2, A.tab_s2, A.tab_e2);
   const float inv = __builtin_amdgcn_rsqf(q);
   const float x = TAB ? __builtin_fmaf(q, inv, -A.tab_off)
@@ -136,13 +157,13 @@ __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>
 
 template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<double>& A,
-                                                 const SplitTable&, double& w1, double& w2) {
-  const double kTwoOverSqrtPi = 1.1283791670955126;
+                                                 const SplitTable<double>& tab, double& w1,
+                                                 double& w2) {
   const double inv = rsqrt(r2 + A.eps2);
   const double r = sqrt(r2);
   const double u = r * A.inv2rs;
   const double e = exp(-u * u);
-  const double f = erfc(u) + kTwoOverSqrtPi * u * e;
+  const double f = split_f64(r2, A, tab);
   const double inv3 = inv * inv * inv;
   const bool pos = r2 > 0.0;                      // eps may be 0
   w1 = pos ? f * inv3 : 0.0;
@@ -161,8 +182,8 @@ __device__ __forceinline__ int wave_inclusive(int v) {
 
 template <typename T, bool VJP>
 struct PairShared {
-  SplitTable tab;                          // FP32 path only; first, so one address
-                                           // register reaches all four arrays
+  SplitTable<T> tab;                       // first, so one address register reaches
+                                           // all coefficient arrays
   typename Vec<T>::v4 jb[kPairCap + 64];   // staged j (+ far sentinels); reused for the reduction
   typename Vec<T>::v4 jl[VJP ? kPairCap + 64 : 1];   // adjoint mode: staged j cotangents
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
@@ -488,9 +509,9 @@ k_pairs(PairArgs<T> A) {
   const int gy0 = ((it.x >> lgd) & md) << lgG;
   const int gz0 = (it.x & md) << lgG;
 
-  if (sizeof(T) == 4 && !COUNT) {      // split-factor table into LDS
-    float* tab = &S.tab.c[0][0];
-    for (int e = lane; e < 4 * kTabStride; e += 64) tab[e] = A.split_tab[e];
+  if (!COUNT) {                        // split-factor table into LDS
+    T* tab = &S.tab.c[0][0];
+    for (int e = lane; e < SplitTable<T>::kCoef * kTabStride; e += 64) tab[e] = A.split_tab[e];
   }
   // i side: the group's G*G z-runs
   {
@@ -547,7 +568,11 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.eps2 = (T)(P->eps * P->eps);
   A.inv2rs = (T)(1.0 / (2.0 * P->r_s));
   A.wscale = -P->prm.G;
-  if (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 8) {
+    A.split_tab = W.split_tab64;
+    A.tab_s64 = kSplitBins / P->r_c;
+  }
+  if constexpr (sizeof(T) == 4) {
     const double s = kSplitBins / (P->tab_v1 - P->tab_v0);
     A.split_tab = W.split_tab;
     A.tab_s = (float)s;

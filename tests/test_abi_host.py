@@ -212,6 +212,27 @@ def test_split_table_matches_erfc_split(b, cutoff_rs, soft_rs, var):
     assert np.max(np.abs(ends - tab[0][1:])) < 2e-7
 
 
+@pytest.mark.parametrize("cutoff_rs", [4.5, 3.0, 6.0])
+def test_split_table64_matches_erfc_split(b, cutoff_rs):
+    """The FP64 table (degree-7 pieces over r) agrees with SciPy's erfc-based f
+    to a few FP64 ulps over all of [0, r_c)."""
+    import numpy as np
+    tab = b.split_table64(cutoff_rs)
+    B = tab.shape[1] - 1
+    r = np.linspace(0.0, cutoff_rs, 300001)[:-1]            # units of r_s
+    x = r * (B / cutoff_rs)
+    k = x.astype(np.int64)
+    tau = 2.0 * (x - k) - 1.0
+    f = tab[7][k]
+    for l in range(6, -1, -1):
+        f = f * tau + tab[l][k]
+    assert np.max(np.abs(f - _split_f(0.5 * r))) < 1e-15
+    assert tab[0][B] == pytest.approx(_split_f(0.5 * cutoff_rs), rel=1e-15)
+    assert np.all(tab[1:, B] == 0)
+    assert b._lib.p3m_split_table64(0.0, None, 0) == -1
+    assert b._lib.p3m_split_table64(4.5, None, 3) == -1
+
+
 def test_split_table_rejects_bad_arguments(b):
     f = b._lib.p3m_split_table
     assert f(0.0, 0.0, None, 0, None) == -1
