@@ -49,11 +49,11 @@ int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32
 
 /* FP64 table of the same split factor f, over r: [0, r_c) is cut into B equal
  * bins; with x = r B / r_c, k = floor(x), tau = 2 (x - k) - 1 in [-1, 1),
- * f = sum_{l=0..7} c_l[k] tau^l, the polynomial through f at the eight
- * Chebyshev points of bin k (fitted in extended precision); entry B is the
- * constant f(r_c). Layout: out[l * (B + 1) + k], l = 0..7, k = 0..B. Returns B
- * and writes the 8 (B + 1) doubles when cap >= 8 (B + 1) (out may be NULL
- * with cap == 0). P3M_EINVAL (-1) for cutoff_rs <= 0 or non-finite, or
+ * f = sum_{l=0..6} c_l[k] tau^l, the degree-6 polynomial through f at the
+ * seven Chebyshev points of bin k (fitted in extended precision; within
+ * 2e-15 of f for cutoff_rs <= 4.5, 2e-14 at 6); entry B is the constant f(r_c). Layout:
+ * out[l * (B + 1) + k], l = 0..6, k = 0..B. Returns B and writes the 7 (B + 1)
+ * doubles when cap >= 7 (B + 1) (out may be NULL with cap == 0). P3M_EINVAL (-1) for cutoff_rs <= 0 or non-finite, or
  * cap > 0 with NULL out. */
 int32_t p3m_split_table64(double cutoff_rs, double* out, int32_t cap);
 

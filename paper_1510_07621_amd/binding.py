@@ -160,14 +160,14 @@ def split_table(cutoff_rs: float, softening_rs: float = 0.0):
 
 
 def split_table64(cutoff_rs: float):
-    """FP64 split-factor table of the pair sum: an (8, B + 1) float64 array,
+    """FP64 split-factor table of the pair sum: a (7, B + 1) float64 array,
     row l the coefficient of tau^l of each bin of r in [0, r_c)."""
     import numpy as np
     b = _lib.p3m_split_table64(cutoff_rs, None, 0)
     _check(min(b, 0), "p3m_split_table64")
-    buf = (ctypes.c_double * (8 * (b + 1)))()
-    _check(min(_lib.p3m_split_table64(cutoff_rs, buf, 8 * (b + 1)), 0), "p3m_split_table64")
-    return np.frombuffer(buf, dtype=np.float64).reshape(8, b + 1).copy()
+    buf = (ctypes.c_double * (7 * (b + 1)))()
+    _check(min(_lib.p3m_split_table64(cutoff_rs, buf, 7 * (b + 1)), 0), "p3m_split_table64")
+    return np.frombuffer(buf, dtype=np.float64).reshape(7, b + 1).copy()
 
 
 @dataclass(frozen=True)

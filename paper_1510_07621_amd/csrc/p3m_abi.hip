@@ -287,7 +287,7 @@ SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out) {
 
 void split_table64(double cutoff_rs, double* out) {
   // Piece k covers u = (k + t) u_c / B, t in [0, 1]; with tau = 2t - 1 the
-  // degree-7 polynomial through f at the eight Chebyshev points of [-1, 1],
+  // degree-6 polynomial through f at the seven Chebyshev points of [-1, 1],
   // solved in extended precision so that only the final rounding to double
   // remains (the pieces are narrow, so the coefficients fall off fast).
   typedef long double LD;

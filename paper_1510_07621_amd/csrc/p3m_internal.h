@@ -26,7 +26,7 @@ constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolatio
 constexpr int kChunk = 128;       // i-particles per pair-loop work item (one wavefront)
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kSplitBins = 64;    // pieces of the split-factor tables
-constexpr int kSplitCoef64 = 8;   // coefficients per piece of the FP64 table (degree 7)
+constexpr int kSplitCoef64 = 7;   // coefficients per piece of the FP64 table (degree 6)
 constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
 
 // One particle in cell order: offsets from its cell's lower corner and mass.

@@ -20,7 +20,8 @@
 // Staging. Per batch of 64 stencil rows each lane resolves one row into at
 // most three contiguous sorted runs (the z-run split where it crosses the
 // periodic box face), a wave scan flattens them, and the wave stages the
-// runs' particles into LDS (kPairCap at a time) as positions relative to the
+// runs' particles into LDS (kPairCap at a time in FP32, half that in FP64) as
+// positions relative to the
 // group's first cell, carrying the periodic shift of the run. Positions are
 // rebuilt from cell-relative offsets and small integer cell differences, so
 // the FP32 path never subtracts two large coordinates.
@@ -32,7 +33,7 @@
 // transcendental; when eps is too large against a piece for the cubic to
 // follow the kink at r = 0, the plan tabulates over r and a square root is
 // added. FP64: the device library's sqrt and rsqrt, and f from 64 pieces of
-// degree 7 over r in [0, r_c) (fitted in extended precision at the Chebyshev
+// degree 6 over r in [0, r_c) (fitted in extended precision at the Chebyshev
 // points of each piece; error at FP64 rounding).
 #include <algorithm>
 
@@ -42,7 +43,13 @@ namespace p3m {
 namespace {
 
 constexpr int kDesc = 3 * 64;          // runs per batch of 64 rows
-constexpr int kStage = kPairCap / 64;  // consecutive staged entries per lane
+// j-particles staged in LDS per pass: kPairCap in FP32; half as many in FP64,
+// so that the workgroup's LDS stays under 1/12 of a CU's (3 waves per SIMD,
+// which its registers allow).
+template <typename T> struct Stage {
+  static constexpr int kCap = sizeof(T) == 4 ? kPairCap : kPairCap / 2;
+  static constexpr int kPer = kCap / 64;   // consecutive staged entries per lane
+};
 // A coordinate far outside any box: its squared separation from any real
 // particle is ~1e37, finite in FP32 and far beyond every cutoff.
 constexpr float kFar = 1e18f;
@@ -81,7 +88,7 @@ struct PairArgs {
 
 // The split-factor table in LDS, one array per coefficient so that the
 // random per-lane bin lookups spread over the banks. FP32: cubic pieces in
-// t in [0, 1); FP64: degree-7 pieces in tau = 2t - 1 in [-1, 1).
+// t in [0, 1); FP64: degree-6 pieces in tau = 2t - 1 in [-1, 1).
 constexpr int kTabStride = kSplitBins + 1;
 template <typename T> struct SplitTable;
 template <> struct SplitTable<float> {
@@ -184,11 +191,12 @@ template <typename T, bool VJP>
 struct PairShared {
   SplitTable<T> tab;                       // first, so one address register reaches
                                            // all coefficient arrays
-  typename Vec<T>::v4 jb[kPairCap + 64];   // staged j (+ far sentinels); reused for the reduction
-  typename Vec<T>::v4 jl[VJP ? kPairCap + 64 : 1];   // adjoint mode: staged j cotangents
+  typename Vec<T>::v4 jb[Stage<T>::kCap + 64];   // staged j (+ far sentinels); reused for
+                                                // the reduction
+  typename Vec<T>::v4 jl[VJP ? Stage<T>::kCap + 64 : 1];   // adjoint mode: staged j cotangents
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
-  int owner[kPairCap];                     // run of each staged entry of a chunk
-  T d_sx[64], d_sy[64];
+  int owner[Stage<T>::kCap];               // run of each staged entry of a chunk
+  int d_rx[64], d_ry[64];                  // x, y cell offsets of each row
   int i_lo[16], i_pre[17];
 };
 
@@ -198,7 +206,7 @@ struct PairShared {
 template <typename T>
 struct RowRuns {
   int cnt[3], lo[3], zs[3];
-  T sx, sy;                                 // x, y shift of the row's column
+  int rx, ry;                               // x, y cell offset of the row's column
 };
 
 template <typename T>
@@ -208,12 +216,12 @@ __device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, int rb,
   const int lg = A.lg, ng = A.ng, mask = ng - 1;
 #pragma unroll
   for (int k = 0; k < 3; ++k) R.cnt[k] = R.lo[k] = R.zs[k] = 0;
-  R.sx = R.sy = T(0);
+  R.rx = R.ry = 0;
   if (rb + lane < A.nrows) {
     const int4 row = A.rows[rb + lane];
     const int jx = (gx0 + row.x) & mask, jy = (gy0 + row.y) & mask;
-    R.sx = T(row.x) * A.h;
-    R.sy = T(row.y) * A.h;
+    R.rx = row.x;
+    R.ry = row.y;
     const int zhi = gz0 + row.w;
     int z = gz0 + row.z;
     const int cbase = ((jx << lg) | jy) << lg;
@@ -240,6 +248,7 @@ template <typename T, int U, bool COUNT, bool UM, int TAB, bool VJP>
 __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJP>& S, int gx0,
                                           int gy0, int gz0, int ibeg, int ni) {
   using T4 = typename Vec<T>::v4;
+  constexpr int kCap = Stage<T>::kCap, kStage = Stage<T>::kPer;
   const int lane = threadIdx.x;
   const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
   const T h = A.h;
@@ -295,15 +304,15 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
         base += cur.cnt[k];
       }
     }
-    S.d_sx[lane] = cur.sx;
-    S.d_sy[lane] = cur.sy;
+    S.d_rx[lane] = cur.rx;
+    S.d_ry[lane] = cur.ry;
     const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
     if (lane == 63) S.d_pre[kDesc] = total;
     if (total == 0 && rb + 64 < A.nrows)          // empty batch: nothing to overlap with
       nxt = resolve_rows<T>(A, rb + 64, lane, gx0, gy0, gz0);
 
-    for (int c0 = 0; c0 < total; c0 += kPairCap) {
-      const int cn = min(kPairCap, total - c0);
+    for (int c0 = 0; c0 < total; c0 += kCap) {
+      const int cn = min(kCap, total - c0);
       __syncthreads();     // descriptors visible; previous chunk done with jb
       // owner[q] = run of chunk entry q: each run marks its first entry in the
       // chunk, then a prefix maximum over the chunk fills the rest
@@ -361,8 +370,8 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
           if (src[e] >= 0) {
             const int d = dd[e];
             T4 o;
-            o.x = S.d_sx[d / 3] + pj[e].x;
-            o.y = S.d_sy[d / 3] + pj[e].y;
+            o.x = T(S.d_rx[d / 3]) * h + pj[e].x;
+            o.y = T(S.d_ry[d / 3]) * h + pj[e].y;
             o.z = T(cz[e] + S.d_zs[d]) * h + pj[e].z;
             o.w = pj[e].w;
             S.jb[q0 + e] = o;
@@ -376,7 +385,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
         far.w = T(0);
         S.jb[cn + lane] = far;
       }
-      if (c0 + kPairCap >= total && rb + 64 < A.nrows)
+      if (c0 + kCap >= total && rb + 64 < A.nrows)
         nxt = resolve_rows<T>(A, rb + 64, lane, gx0, gy0, gz0);   // in flight during the loop
       __syncthreads();
       // lane (set, stream) takes staged entries st, st + ns, ...; the trip
