@@ -20,6 +20,7 @@ ewald      O-EW: direct periodic summation by the Ewald method (the truth)
 integrate  kick and drift updates
 metrics    per-particle relative force-error statistics
 cosmology  background expansion and the comoving kick/drift coefficients
+powerspec  power spectrum of the particle density on the PM grid, sigma(R)
 adjoint    VJP of the force (pair Hessian-vector sum; mesh adjoint) and of
            the kick-drift-kick leapfrog
 
@@ -27,4 +28,4 @@ Array conventions: positions, momenta, accelerations and forces are float64
 arrays of shape (3, N) (structure of arrays, as in the guide's snapshot
 layout); masses are a float64 array of shape (N,) or a scalar.
 """
-from . import split, pp, pm, p3m, ewald, integrate, metrics, cosmology, adjoint  # noqa: F401
+from . import split, pp, pm, p3m, ewald, integrate, metrics, cosmology, adjoint, powerspec  # noqa: F401
