@@ -147,6 +147,29 @@ int pm_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mas
 int pp_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
                  double mass_scalar, const double* force_bar, double* pos_bar);
 
+/* Power spectrum of the particle density on the plan's PM grid (guide Ch. 5:
+ * PM_gridsize is also the power-spectrum grid, R_tophat the radius of the
+ * top-hat for sigma; Ch. 8 powerspec test). The guide gives no estimator;
+ * this one: the CIC deposit rho of the force path, delta = rho / rho_bar - 1,
+ * P(k) = box^3 |FFT(delta)_k|^2 / grid_n^6 for k != 0, divided by W(k)^2 (the
+ * CIC window, W = prod_d sinc^2(pi n_d / grid_n)) unless the plan's
+ * deconv_power is 0. Shells of unit width in |n| (k = 2 pi n / box): shell b
+ * holds the modes with b + 1/2 <= |n| < b + 3/2, b = 0 .. nbins - 1, counted
+ * over the full k-space. sigma^2(R) = box^-3 sum_{k != 0} P(k) W_TH(k R)^2
+ * over all grid modes, W_TH(x) = 3 (sin x - x cos x) / x^3 (R = 0: the grid
+ * variance of delta).
+ *   pos, mass, mass_scalar  as for p3m_force (n >= 1, positive total mass)
+ *   nbins       1 .. 512
+ *   r_tophat    R >= 0, a length
+ *   k_out, power_out, modes_out   device double [nbins]: the shell's mean |k|,
+ *               mean P and number of modes (0, 0, 0 for an empty shell)
+ *   sigma_out   device double [1] or NULL
+ * The FFT runs in the plan's precision; the sums in double. EINVAL for
+ * n < 1, a bad nbins or r_tophat, null outputs or a non-positive scalar mass. */
+int p3m_power_spectrum(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+                       double mass_scalar, int32_t nbins, double r_tophat, double* k_out,
+                       double* power_out, double* modes_out, double* sigma_out);
+
 /* Count the ordered pairs (i, j != i) with minimum-image separation in
  * (0, r_c), the pairs the short-range sum evaluates (a diagnostic for
  * interaction rates). count_out: device int64 [1], overwritten. Separations

@@ -61,6 +61,8 @@ def _load():
         "pp_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "p3m_pair_count": (ctypes.c_int, [vp, i64, vp, vp]),
         "p3m_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
+        "p3m_power_spectrum": (ctypes.c_int, [vp, i64, vp, vp, dbl, i32, dbl, vp, vp, vp,
+                                              vp]),
         "pm_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
         "pp_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
         "p3m_drift_vjp": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, vp]),
@@ -322,6 +324,20 @@ class Plan:
 
     def pp_force_vjp(self, pos, mass, force_bar, out=None):
         return self._vjp(_lib.pp_force_vjp, "pp_force_vjp", pos, mass, force_bar, out)
+
+    def power_spectrum(self, pos, mass=None, nbins=None, r_tophat=0.0):
+        """(k, P, modes, sigma) of the particle density on the plan's grid:
+        shell-mean |k|, shell-mean power and mode count per unit-width shell
+        in |n| (nbins, default grid_n / 2), and sigma(r_tophat); device float64."""
+        n = _vec3(pos, "pos")
+        m, ms = _mass(mass, n)
+        nb = int(nbins if nbins is not None else self.params.grid_n // 2)
+        out = torch.empty((3, max(nb, 1)), dtype=torch.float64, device=pos.device)
+        sig = torch.empty(1, dtype=torch.float64, device=pos.device)
+        _check(_lib.p3m_power_spectrum(self._handle(), n, _ptr(pos), _ptr(m), ms, nb,
+                                       float(r_tophat), _ptr(out[0]), _ptr(out[1]),
+                                       _ptr(out[2]), _ptr(sig)), "p3m_power_spectrum")
+        return out[0], out[1], out[2], sig[0]
 
     def pair_count(self, pos) -> int:
         """Ordered pairs with 0 < r < r_c (synchronises to return the count)."""

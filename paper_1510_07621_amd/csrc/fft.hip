@@ -232,6 +232,101 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   }
 }
 
+// Power spectrum: forward x transform of one y-row and a chunk of kc
+// kz-columns (after the z and y forward passes), then each mode's |rho_k|^2,
+// divided by W(k)^2 when deconvolving, is added with its full-space
+// multiplicity (1 on the kz = 0 and Nyquist planes, else 2) into its shell
+// b = floor(|n| - 1/2): acc = [power sums | |n| sums | mode counts][nbins],
+// then the top-hat-weighted sum for sigma and rho_0 (the k = 0 value).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
+              const typename Vec<T>::v2* __restrict__ tw, int deconv, int nbins, double kr_unit,
+              double* __restrict__ acc) {
+  using T2 = typename Vec<T>::v2;
+  extern __shared__ unsigned char smem_raw[];
+  T2* buf = reinterpret_cast<T2*>(smem_raw);
+  __shared__ double hist[3 * kMaxPowerBins + 1];
+  const int M1 = (ng >> 1) + 1;
+  const int nchunk = (M1 + kc - 1) / kc;
+  const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
+  const int kn = min(kc, M1 - kz0);
+  const int64_t xs = (int64_t)ng * M1;
+  const T2* col = spec + (int64_t)y * M1 + kz0;
+  for (int i = threadIdx.x; i < 3 * nbins + 1; i += kThreads) hist[i] = 0.0;
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    int x = idx / kc, c = idx - x * kc;
+    T2 v;
+    if (c < kn) v = col[x * xs + c]; else { v.x = T(0); v.y = T(0); }
+    buf[c * ng + brev(x, lg)] = v;
+  }
+  __syncthreads();
+  fft_dit<T, false>(buf, kc, ng, lg, tw, ng);     // ends with a barrier
+  const int half = ng >> 1;
+  const int ny = y < half ? y : y - ng;
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    const int c = idx >> lg, kx = idx & (ng - 1), kz = kz0 + c;
+    if (c >= kn) continue;
+    const int nx = kx < half ? kx : kx - ng;
+    const T2 v = buf[idx];
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    if (n2 == 0) {
+      acc[3 * nbins + 1] = (double)v.x;             // rho_0: one thread of one block
+      continue;
+    }
+    double pw = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    if (deconv) {
+      double w = 1.0;
+      const int nn[3] = {nx, ny, kz};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (nn[d] != 0) {
+          const double a = (double)nn[d] / ng;
+          const double sc = sinpi(a) / (M_PI * a);
+          w *= sc * sc;
+        }
+      pw /= w * w;
+    }
+    const double mult = (kz == 0 || kz == half) ? 1.0 : 2.0;
+    const double nabs = sqrt((double)n2);
+    const int b = (int)floor(nabs - 0.5);
+    if (b >= 0 && b < nbins) {
+      atomicAdd(&hist[b], mult * pw);
+      atomicAdd(&hist[nbins + b], mult * nabs);
+      atomicAdd(&hist[2 * nbins + b], mult);
+    }
+    const double x = kr_unit * nabs;
+    double wt;
+    if (x < 1e-3) {
+      wt = 1.0 - x * x / 10.0;
+    } else {
+      double sx, cx;
+      sincos(x, &sx, &cx);
+      wt = 3.0 * (sx - x * cx) / (x * x * x);
+    }
+    atomicAdd(&hist[3 * nbins], mult * pw * wt * wt);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * nbins + 1; i += kThreads)
+    if (hist[i] != 0.0) atomicAdd(&acc[i], hist[i]);
+}
+
+// Shell averages and sigma from the accumulated sums.
+__global__ void __launch_bounds__(256)
+k_power_finish(const double* __restrict__ acc, int nbins, double box, double* __restrict__ k_out,
+               double* __restrict__ p_out, double* __restrict__ m_out,
+               double* __restrict__ sigma_out) {
+  const double rho0 = acc[3 * nbins + 1];
+  const double inv2 = 1.0 / (rho0 * rho0);
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const double m = acc[2 * nbins + b];
+    m_out[b] = m;
+    p_out[b] = m > 0 ? box * box * box * acc[b] * inv2 / m : 0.0;
+    k_out[b] = m > 0 ? 2.0 * M_PI / box * acc[nbins + b] / m : 0.0;
+  }
+  if (threadIdx.x == 0 && sigma_out) sigma_out[0] = sqrt(acc[3 * nbins] * inv2);
+}
+
 template <typename T>
 __global__ void k_tables(int ng, double box, double r_s, int deconv_power,
                          typename Vec<T>::v2* __restrict__ tw, T* __restrict__ etab,
@@ -308,9 +403,43 @@ hipError_t launch_fft_poisson(p3m_plan* P) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_power_spectrum(p3m_plan* P, int nbins, double r_tophat, double* k_out,
+                                 double* p_out, double* m_out, double* sigma_out) {
+  using T2 = typename Vec<T>::v2;
+  Workspace& W = P->ws;
+  const int ng = P->ng, lg = P->lg, M = ng / 2, M1 = M + 1;
+  const T2* tw = (const T2*)W.twiddle;
+  T2* spec = (T2*)W.spec;
+  hipStream_t s = P->stream;
+  hipError_t e = launch_fill_i32((int32_t*)W.power_acc, 2 * (3 * nbins + 2), 0, s);
+  if (e != hipSuccess) return e;
+  int nl = pow2_floor(kLdsElems / M);
+  if (nl > ng * ng) nl = ng * ng;
+  size_t lds_z = (size_t)nl * M * sizeof(T2);
+  unsigned blocks_z = (unsigned)((int64_t)ng * ng / nl);
+  int kc = kLdsElems / ng;
+  if (kc > 16) kc = 16;
+  if (kc < 1) kc = 1;
+  size_t lds_c = (size_t)kc * ng * sizeof(T2);
+  unsigned nchunk = (unsigned)((M1 + kc - 1) / kc);
+  k_fft_z_r2c<T><<<blocks_z, kThreads, lds_z, s>>>((const T*)W.grid, spec, ng, lg, nl, tw);
+  k_fft_y<T, false><<<ng * nchunk, kThreads, lds_c, s>>>(spec, ng, lg, kc, tw);
+  k_fft_x_power<T><<<ng * nchunk, kThreads, lds_c, s>>>(
+      spec, ng, lg, kc, tw, P->prm.deconv_power != 0 ? 1 : 0, nbins,
+      2.0 * M_PI / P->prm.box * r_tophat, W.power_acc);
+  k_power_finish<<<1, 256, 0, s>>>(W.power_acc, nbins, P->prm.box, k_out, p_out, m_out,
+                                   sigma_out);
+  return hipGetLastError();
+}
+
 template hipError_t launch_tables<float>(p3m_plan*);
 template hipError_t launch_tables<double>(p3m_plan*);
 template hipError_t launch_fft_poisson<float>(p3m_plan*);
 template hipError_t launch_fft_poisson<double>(p3m_plan*);
+template hipError_t launch_power_spectrum<float>(p3m_plan*, int, double, double*, double*,
+                                                 double*, double*);
+template hipError_t launch_power_spectrum<double>(p3m_plan*, int, double, double*, double*,
+                                                  double*, double*);
 
 }  // namespace p3m

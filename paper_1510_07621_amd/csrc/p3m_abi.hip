@@ -44,7 +44,7 @@ void free_workspace(p3m_plan* P) {
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
                   W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.split_tab64, W.lam,
-                  W.grid2, W.lam_grid};
+                  W.grid2, W.lam_grid, W.power_acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -482,6 +482,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   W.counter = dev_alloc<unsigned long long>(1, err);
   W.split_tab = dev_alloc<float>(4 * (kSplitBins + 1), err);
   W.split_tab64 = dev_alloc<double>(kSplitCoef64 * (kSplitBins + 1), err);
+  W.power_acc = dev_alloc<double>(3 * kMaxPowerBins + 2, err);
   if (q.adjoint) {
     W.lam = dev_alloc<unsigned char>(nn * 4 * real, err);
     W.grid2 = dev_alloc<unsigned char>(P->ncell * real, err);
@@ -566,6 +567,34 @@ int pm_force_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass,
 int pp_force_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass,
                  double mass_scalar, const double* force_bar, double* pos_bar) {
   return vjp_entry(P, n, pos, mass, mass_scalar, force_bar, pos_bar, Part::kPP);
+}
+
+int p3m_power_spectrum(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                       double mass_scalar, int32_t nbins, double r_tophat, double* k_out,
+                       double* power_out, double* modes_out, double* sigma_out) {
+  if (!P || n <= 0 || n > P->n_max || !pos) return P3M_EINVAL;
+  if (nbins < 1 || nbins > kMaxPowerBins) return P3M_EINVAL;
+  if (!(r_tophat >= 0) || !std::isfinite(r_tophat)) return P3M_EINVAL;
+  if (!k_out || !power_out || !modes_out) return P3M_EINVAL;
+  if (!mass && !(mass_scalar > 0 && std::isfinite(mass_scalar))) return P3M_EINVAL;
+  begin_call(P);
+  hipError_t e;
+  {
+    StageTimer t(P, P3M_STAGE_BIN);
+    if ((e = launch_bin(P, n, pos, mass, mass_scalar)) != hipSuccess) return status_of(e);
+  }
+  const bool f32 = P->prm.precision == P3M_FP32;
+  {
+    StageTimer t(P, P3M_STAGE_DEPOSIT);
+    e = f32 ? launch_deposit<float>(P) : launch_deposit<double>(P);
+    if (e != hipSuccess) return status_of(e);
+  }
+  StageTimer t(P, P3M_STAGE_FFT);
+  e = f32 ? launch_power_spectrum<float>(P, nbins, r_tophat, k_out, power_out, modes_out,
+                                         sigma_out)
+          : launch_power_spectrum<double>(P, nbins, r_tophat, k_out, power_out, modes_out,
+                                          sigma_out);
+  return status_of(e);
 }
 
 int p3m_pair_count(p3m_plan* P, int64_t n, const double* pos, int64_t* count_out) {

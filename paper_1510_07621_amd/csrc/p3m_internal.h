@@ -28,6 +28,7 @@ constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one 
 constexpr int kSplitBins = 64;    // pieces of the split-factor tables
 constexpr int kSplitCoef64 = 7;   // coefficients per piece of the FP64 table (degree 6)
 constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
+constexpr int kMaxPowerBins = 512;     // shells of the power spectrum
 
 // One particle in cell order: offsets from its cell's lower corner and mass.
 // (x, y, z, m) as float4 (FP32 path) or double4 (FP64 path).
@@ -53,6 +54,7 @@ struct Workspace {
   unsigned long long* counter = nullptr;  // [1] pair-count scratch
   float* split_tab = nullptr;   // [4][kSplitBins + 1] cubic pieces of f on [0, r_c)
   double* split_tab64 = nullptr;  // [kSplitCoef64][kSplitBins + 1] FP64 pieces of f(r)
+  double* power_acc = nullptr;  // [3 * kMaxPowerBins + 2] power-spectrum sums
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
   void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
@@ -112,6 +114,10 @@ template <typename T>
 hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
 template <typename T>
 hipError_t launch_tables(p3m_plan* P);
+
+template <typename T>
+hipError_t launch_power_spectrum(p3m_plan* P, int nbins, double r_tophat, double* k_out,
+                                 double* p_out, double* m_out, double* sigma_out);
 
 // Adjoint stages (workspace of plans created with params.adjoint != 0).
 template <typename T>

@@ -98,6 +98,7 @@ def test_calls_on_null_plan_and_bad_arguments(b):
     assert L.p3m_drift(0, None, None, None, 1.0, 1.0, 1.0, None) == 0
     assert L.p3m_drift(5, 1, 1, None, 1.0, 1.0, 0.0, None) == -1     # box <= 0
     assert L.p3m_drift(5, 1, 1, None, 0.0, 1.0, 1.0, None) == -1     # zero scalar mass
+    assert L.p3m_power_spectrum(None, 10, 1, None, 1.0, 8, 0.0, 2, 3, 4, None) == -1
     for fn in (L.p3m_force_vjp, L.pm_force_vjp, L.pp_force_vjp):
         assert fn(None, 10, 1, None, 1.0, 2, 3) == -1
     assert L.p3m_drift_vjp(-1, 1, 2, None, 1.0, 1.0, None) == -1
