@@ -156,6 +156,35 @@ def adjoint_leg(binding, torch, name, precision, segment=None, keep_grad=False):
             "grad_rms": float(torch.sqrt((g * g).sum(0).mean()))}
 
 
+def powerspec_leg(binding, torch, w, pos, calls=20):
+    """Time of one power-spectrum call (binning, CIC deposit, forward FFT with
+    shell binning) on the workload, FP32, grid_n / 2 shells, sigma at 8 cells,
+    and its rate against HBM: algorithmic bytes 60 N (sort and pack 40 N,
+    deposit reads 20 N) + 24 M (deposit write 4 M, z pass 4 + 4 M, y pass
+    4 + 4 M, x pass 4 M; M = grid cells, 4-byte reals)."""
+    P = binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
+                                    cutoff_rs=w.cutoff_rs, softening=w.softening, G=w.G,
+                                    precision="fp32"), w.n)
+    x = torch.as_tensor(pos, device="cuda").contiguous()
+    R = 8.0 * w.h
+    for _ in range(3):
+        P.power_spectrum(x, w.mass, r_tophat=R)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(calls):
+        k, p, m, sig = P.power_spectrum(x, w.mass, r_tophat=R)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    P.close()
+    nbytes = 60.0 * w.n + 24.0 * w.grid_n ** 3
+    return {"workload": w.name, "ms_per_call": ms, "algorithmic_bytes": nbytes,
+            "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "sigma_8cells": float(sig)}
+
+
 def cpu_leg(binding, torch, w, pos, n_sample):
     """CPU oracle timed on a bounded sample, plus the GPU force error against it."""
     from oracle import metrics
@@ -260,6 +289,7 @@ def main():
             "pp_frac_of_fp64_peak": r64["pairs"] * FLOP_PER_PAIR / (pp64 * 1e-3) / 1e12
                                     / FP64_PEAK_TFLOPS,
         }
+    out["powerspec"] = powerspec_leg(binding, torch, w, pos)
     if not args.no_adjoint:
         legs = [adjoint_leg(binding, torch, "zeldovich64_kdk", "fp64", segment=1),
                 adjoint_leg(binding, torch, "plummer128_kdk", "fp32")]

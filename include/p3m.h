@@ -71,6 +71,8 @@ typedef struct p3m_params {
   double  softening;    /* Plummer radius eps as a length, >= 0                      */
   double  G;            /* gravitational constant                                    */
   int32_t adjoint;      /* 1: also allocate the workspace of the *_force_vjp calls   */
+  int32_t ewald_gridsize; /* ewald_gridsize: 0, or even in 8..512 to tabulate the
+                             Ewald correction of pp_ewald_force                    */
 } p3m_params;
 
 /* Opaque plan: derived geometry, device workspace, and optional stage timers. */
@@ -78,14 +80,15 @@ typedef struct p3m_plan p3m_plan;
 
 /* Fill *out with the documented defaults for a grid of grid_n^3 cells in a
  * box of side box: FP32, fd_order 4, deconv_power 2, rs_cells 1.25,
- * cutoff_rs 4.5, softening 0, G 1, adjoint 0. Returns P3M_EINVAL for a null
- * out. */
+ * cutoff_rs 4.5, softening 0, G 1, adjoint 0, ewald_gridsize 0. Returns
+ * P3M_EINVAL for a null out. */
 int p3m_params_default(p3m_params* out, int32_t grid_n, double box);
 
 /* Create a plan for up to n_max particles whose work runs on hip_stream
  * (a hipStream_t; NULL = the null stream). Validates the parameters
  * (EINVAL for a non-power-of-two or out-of-range grid, box <= 0,
  * rs_cells <= 0, cutoff_rs <= 0, softening < 0, adjoint not 0 or 1,
+ * ewald_gridsize not 0 or even in 8..512,
  * n_max < 0 or n_max >= 2^31; ERANGE when r_c >= box/2), then allocates the
  * workspace (with adjoint = 1 also that of the VJP calls: one more real grid,
  * three cotangent grids and a sorted cotangent array)
@@ -169,6 +172,26 @@ int pp_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mas
 int p3m_power_spectrum(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
                        double mass_scalar, int32_t nbins, double r_tophat, double* k_out,
                        double* power_out, double* modes_out, double* sigma_out);
+
+/* PP gravity with a tabulated Ewald correction (guide Ch. 5: use_Ewald,
+ * ewald_gridsize; Ch. 8 kick_PP_with_Ewald test), all pairs, FP64, for
+ * small-N validation (cost O(n^2)):
+ *   F_i = -G m_i sum_{j != i} m_j [ r / (r^2 + eps^2)^(3/2) + c(r) ],
+ * r the minimum-image separation, c(r) = e(r) - r / |r|^3 the correction of
+ * the periodic field e of a unit mass with its images in a neutralising
+ * background (Ewald sum, as a multiple of -G), tabulated by the plan on the
+ * ewald_gridsize^3 node grid (spacing box / ewald_gridsize; c is odd in each
+ * coordinate, so the octant [0, box/2]^3 is stored) and interpolated
+ * trilinearly. Softening acts on the minimum-image term only. Arguments as
+ * for p3m_force; the plan must have ewald_gridsize > 0 (else EINVAL). */
+int pp_ewald_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+                   double mass_scalar, void* force, int32_t force_fp32);
+
+/* The tabulated correction c(r) of pp_ewald_force at npts separations
+ * r (device double [3][npts], reduced to the minimum image), written to
+ * c_out (device double [3][npts], not overlapping r). For testing the table;
+ * EINVAL without a table. */
+int p3m_ewald_correction(p3m_plan* plan, int64_t npts, const double* r, double* c_out);
 
 /* Count the ordered pairs (i, j != i) with minimum-image separation in
  * (0, r_c), the pairs the short-range sum evaluates (a diagnostic for

@@ -35,6 +35,7 @@ class P3MParams(ctypes.Structure):
         ("softening", ctypes.c_double),
         ("G", ctypes.c_double),
         ("adjoint", ctypes.c_int32),
+        ("ewald_gridsize", ctypes.c_int32),
     ]
 
 
@@ -61,6 +62,8 @@ def _load():
         "pp_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "p3m_pair_count": (ctypes.c_int, [vp, i64, vp, vp]),
         "p3m_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
+        "pp_ewald_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
+        "p3m_ewald_correction": (ctypes.c_int, [vp, i64, vp, vp]),
         "p3m_power_spectrum": (ctypes.c_int, [vp, i64, vp, vp, dbl, i32, dbl, vp, vp, vp,
                                               vp]),
         "pm_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
@@ -231,6 +234,7 @@ class Params:
     fd_order: int = 4
     deconv_power: int = 2
     adjoint: bool = False        # also allocate the workspace of the VJP calls
+    ewald_gridsize: int = 0      # > 0: tabulate the Ewald correction (pp_ewald_force)
 
     def to_c(self) -> P3MParams:
         if self.precision not in ("fp32", "fp64"):
@@ -239,7 +243,8 @@ class Params:
                          P3M_FP32 if self.precision == "fp32" else P3M_FP64,
                          int(self.fd_order), int(self.deconv_power), float(self.box),
                          float(self.rs_cells), float(self.cutoff_rs),
-                         float(self.softening), float(self.G), 1 if self.adjoint else 0)
+                         float(self.softening), float(self.G), 1 if self.adjoint else 0,
+                         int(self.ewald_gridsize))
 
 
 class Plan:
@@ -324,6 +329,19 @@ class Plan:
 
     def pp_force_vjp(self, pos, mass, force_bar, out=None):
         return self._vjp(_lib.pp_force_vjp, "pp_force_vjp", pos, mass, force_bar, out)
+
+    def pp_ewald_force(self, pos, mass=None, out=None, fp32_out=False):
+        """All-pairs PP force with the tabulated Ewald correction (plan made
+        with Params(ewald_gridsize=E)), shape (3, n)."""
+        return self._force(_lib.pp_ewald_force, "pp_ewald_force", pos, mass, out, fp32_out)
+
+    def ewald_correction(self, r):
+        """Tabulated correction c(r) at separations r ((3, npts) float64)."""
+        npts = _vec3(r, "r")
+        out = torch.empty_like(r)
+        _check(_lib.p3m_ewald_correction(self._handle(), npts, _ptr(r), _ptr(out)),
+               "p3m_ewald_correction")
+        return out
 
     def power_spectrum(self, pos, mass=None, nbins=None, r_tophat=0.0):
         """(k, P, modes, sigma) of the particle density on the plan's grid:

@@ -44,7 +44,7 @@ void free_workspace(p3m_plan* P) {
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
                   W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.split_tab64, W.lam,
-                  W.grid2, W.lam_grid, W.power_acc};
+                  W.grid2, W.lam_grid, W.power_acc, W.ewald_tab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -432,6 +432,9 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   if (!std::isfinite(q.G)) return P3M_EINVAL;
   if (n_max < 0 || n_max >= (int64_t{1} << 31)) return P3M_EINVAL;
   if (q.adjoint != 0 && q.adjoint != 1) return P3M_EINVAL;
+  if (q.ewald_gridsize != 0 &&
+      (q.ewald_gridsize < 8 || q.ewald_gridsize > 512 || (q.ewald_gridsize & 1)))
+    return P3M_EINVAL;
   const double h = q.box / q.grid_n;
   const double r_s = q.rs_cells * h;
   const double r_c = q.cutoff_rs * r_s;
@@ -483,6 +486,10 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   W.split_tab = dev_alloc<float>(4 * (kSplitBins + 1), err);
   W.split_tab64 = dev_alloc<double>(kSplitCoef64 * (kSplitBins + 1), err);
   W.power_acc = dev_alloc<double>(3 * kMaxPowerBins + 2, err);
+  if (q.ewald_gridsize) {
+    const int64_t H = q.ewald_gridsize / 2 + 1;
+    W.ewald_tab = dev_alloc<double4>(H * H * H, err);
+  }
   if (q.adjoint) {
     W.lam = dev_alloc<unsigned char>(nn * 4 * real, err);
     W.grid2 = dev_alloc<unsigned char>(P->ncell * real, err);
@@ -514,6 +521,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   }
   if (err == hipSuccess)
     err = q.precision == P3M_FP32 ? launch_tables<float>(P) : launch_tables<double>(P);
+  if (err == hipSuccess && q.ewald_gridsize) err = launch_ewald_table(P);
   if (err == hipSuccess) err = hipStreamSynchronize(P->stream);
   if (err != hipSuccess) {
     free_workspace(P);
@@ -595,6 +603,30 @@ int p3m_power_spectrum(p3m_plan* P, int64_t n, const double* pos, const double* 
           : launch_power_spectrum<double>(P, nbins, r_tophat, k_out, power_out, modes_out,
                                           sigma_out);
   return status_of(e);
+}
+
+int pp_ewald_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                   double mass_scalar, void* force, int32_t force_fp32) {
+  if (!P || n < 0 || n > P->n_max || !P->prm.ewald_gridsize) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!pos || !force) return P3M_EINVAL;
+  if (!mass && !std::isfinite(mass_scalar)) return P3M_EINVAL;
+  size_t fbytes = (size_t)(3 * n) * (force_fp32 ? sizeof(float) : sizeof(double));
+  if (overlaps(force, fbytes, pos, (size_t)(3 * n) * sizeof(double)) ||
+      overlaps(force, fbytes, mass, (size_t)n * sizeof(double)))
+    return P3M_EINVAL;
+  P->timing_slot = -1;
+  return status_of(launch_pp_ewald(P, n, pos, mass, mass_scalar, force, force_fp32 ? 1 : 0));
+}
+
+int p3m_ewald_correction(p3m_plan* P, int64_t npts, const double* r, double* c_out) {
+  if (!P || npts < 0 || !P->prm.ewald_gridsize) return P3M_EINVAL;
+  if (npts == 0) return P3M_OK;
+  if (!r || !c_out ||
+      overlaps(r, (size_t)(3 * npts) * sizeof(double), c_out,
+               (size_t)(3 * npts) * sizeof(double)))
+    return P3M_EINVAL;
+  return status_of(launch_ewald_eval(P, npts, r, c_out));
 }
 
 int p3m_pair_count(p3m_plan* P, int64_t n, const double* pos, int64_t* count_out) {

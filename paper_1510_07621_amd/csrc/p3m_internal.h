@@ -55,6 +55,7 @@ struct Workspace {
   float* split_tab = nullptr;   // [4][kSplitBins + 1] cubic pieces of f on [0, r_c)
   double* split_tab64 = nullptr;  // [kSplitCoef64][kSplitBins + 1] FP64 pieces of f(r)
   double* power_acc = nullptr;  // [3 * kMaxPowerBins + 2] power-spectrum sums
+  void* ewald_tab = nullptr;    // [(E/2+1)^3] double4 Ewald correction octant (E > 0)
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
   void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
@@ -115,6 +116,10 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
 template <typename T>
 hipError_t launch_tables(p3m_plan* P);
 
+hipError_t launch_ewald_table(p3m_plan* P);
+hipError_t launch_pp_ewald(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                           double ms, void* force, int force_fp32);
+hipError_t launch_ewald_eval(p3m_plan* P, int64_t npts, const double* r, double* out);
 template <typename T>
 hipError_t launch_power_spectrum(p3m_plan* P, int nbins, double r_tophat, double* k_out,
                                  double* p_out, double* m_out, double* sigma_out);

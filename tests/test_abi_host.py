@@ -76,6 +76,9 @@ def test_plan_create_rejects_bad_sizes_and_nulls(b):
     bad = b.Params(grid_n=32, precision="fp32").to_c()
     bad.precision = 7
     assert b._lib.p3m_plan_create(ctypes.byref(bad), 4, None, ctypes.byref(h)) == -1
+    for E in (6, 7, 514, -2):
+        bad = b.Params(grid_n=32, ewald_gridsize=E).to_c()
+        assert b._lib.p3m_plan_create(ctypes.byref(bad), 4, None, ctypes.byref(h)) == -1
     bad = b.Params(grid_n=32, adjoint=True).to_c()
     assert bad.adjoint == 1
     bad.adjoint = 2
@@ -99,6 +102,8 @@ def test_calls_on_null_plan_and_bad_arguments(b):
     assert L.p3m_drift(5, 1, 1, None, 1.0, 1.0, 0.0, None) == -1     # box <= 0
     assert L.p3m_drift(5, 1, 1, None, 0.0, 1.0, 1.0, None) == -1     # zero scalar mass
     assert L.p3m_power_spectrum(None, 10, 1, None, 1.0, 8, 0.0, 2, 3, 4, None) == -1
+    assert L.pp_ewald_force(None, 10, 1, None, 1.0, 2, 0) == -1
+    assert L.p3m_ewald_correction(None, 10, 1, 2) == -1
     for fn in (L.p3m_force_vjp, L.pm_force_vjp, L.pp_force_vjp):
         assert fn(None, 10, 1, None, 1.0, 2, 3) == -1
     assert L.p3m_drift_vjp(-1, 1, 2, None, 1.0, 1.0, None) == -1
