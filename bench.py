@@ -185,6 +185,29 @@ def powerspec_leg(binding, torch, w, pos, calls=20):
             "sigma_8cells": float(sig)}
 
 
+def ewald_leg(binding, torch, calls=5):
+    """All-pairs PP force with the tabulated Ewald correction (64^3 table) on
+    the 32^3 uniform workload, FP64: time per call and ordered pairs/s."""
+    from paper_1510_07621_amd import ics
+    w = ics.workload("uniform32")
+    P = binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, softening=w.softening, G=w.G,
+                                    precision="fp64", ewald_gridsize=64), w.n)
+    x = torch.as_tensor(w.positions(), device="cuda").contiguous()
+    F = P.pp_ewald_force(x, w.mass)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(calls):
+        P.pp_ewald_force(x, w.mass, out=F)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    P.close()
+    pairs = float(w.n) * (w.n - 1)
+    return {"workload": w.name, "ewald_gridsize": 64, "ms_per_call": ms,
+            "pairs_per_s": pairs / (ms * 1e-3)}
+
+
 def cpu_leg(binding, torch, w, pos, n_sample):
     """CPU oracle timed on a bounded sample, plus the GPU force error against it."""
     from oracle import metrics
@@ -290,6 +313,7 @@ def main():
                                     / FP64_PEAK_TFLOPS,
         }
     out["powerspec"] = powerspec_leg(binding, torch, w, pos)
+    out["pp_ewald"] = ewald_leg(binding, torch)
     if not args.no_adjoint:
         legs = [adjoint_leg(binding, torch, "zeldovich64_kdk", "fp64", segment=1),
                 adjoint_leg(binding, torch, "plummer128_kdk", "fp32")]
