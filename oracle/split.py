@@ -2,10 +2,9 @@
 
 The guide splits gravity at a scale r_s (PM_scale, in PM cells) into a
 long-range part solved on the mesh and a short-range part summed over pairs
-closer than a cutoff r_c (P3M_cutoff, in units of r_s), and states that a
-cutoff of at least 4.8 r_s leaves less than one percent of the force
-unaccounted for (CONCEPT User's Guide, Ch. 5 "Parameters", entries PM_scale
-and P3M_cutoff). The functional form is not given; the reading taken here is
+closer than a cutoff r_c (P3M_cutoff, in units of r_s); by its Ch. 5, cutting
+off at 4.8 r_s or beyond drops under one percent of the force (CONCEPT User's
+Guide, Ch. 5 "Parameters", entries PM_scale and P3M_cutoff). The functional form is not given; the reading taken here is
 the Gaussian split, the one common convention that matches that statement:
 
     long range:  potential kernel  exp(-k^2 r_s^2) / k^2     (Fourier space)

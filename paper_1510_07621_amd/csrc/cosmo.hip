@@ -1,7 +1,7 @@
 // Background cosmology for comoving kick and drift coefficients (host code).
 //
 // The guide evolves comoving positions and momenta (Ch. 6) over a global
-// time step given as a fraction of the instantaneous age of the universe
+// time step set as a fraction of the current age of the universe
 // (Ch. 5, Delta t_factor), with the background set by H0, Omega_m,
 // Omega_Lambda and a_begin (Ch. 5, cosmological parameters). With canonical
 // momenta p = a^2 m dx/dt and the force F = -m grad(phi) of the comoving

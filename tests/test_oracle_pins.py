@@ -31,7 +31,7 @@ def _golden(name):
 # ---------------------------------------------------------------- split factor
 
 def test_split_cutoff_statement_of_the_guide():
-    """Guide Ch. 5, P3M_cutoff: >= 4.8 split scales leaves < 1 % unaccounted.
+    """Guide Ch. 5, P3M_cutoff: a cutoff >= 4.8 split scales drops < 1 % of the force.
 
     The reading (Gaussian split, u = r / 2 r_s) must make 4.8 the threshold:
     below 1 % at 4.8, above it a little earlier."""
