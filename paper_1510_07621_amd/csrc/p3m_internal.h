@@ -23,7 +23,7 @@ template <> struct Vec<double> {
 
 constexpr int kPairCap = 256;     // j-particles staged in LDS per pass of the pair loop
 constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
-constexpr int kChunk = 128;       // i-particles per pair-loop work item (one wavefront)
+constexpr int kChunk = 64;        // i-particles per pair-loop work item (one wavefront)
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kSplitBins = 64;    // pieces of the split-factor tables
 constexpr int kSplitCoef64 = 7;   // coefficients per piece of the FP64 table (degree 6)

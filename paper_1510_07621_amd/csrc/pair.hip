@@ -4,7 +4,7 @@
 //   f(r) = erfc(u) + (2u / sqrt(pi)) exp(-u^2),  u = r / (2 r_s)
 //
 // Work decomposition. The grid's cells are grouped into i-groups of G^3
-// cells; a work item is (group, chunk) with up to kChunk (128) of the
+// cells; a work item is (group, chunk) with up to kChunk (64) of the
 // group's particles, one wavefront per item. The j-candidates of a group are the
 // particles of every cell whose box comes closer than r_c to the group's box
 // (the stencil rows: z-runs of cells, precomputed per plan).
@@ -14,7 +14,7 @@
 // scarce resource of a cutoff test. With n_i particles the wave has
 // n_u = ceil(n_i / U) slot-sets and s = 64 / n_u streams: lane (set, stream)
 // takes every s-th staged j, so small groups still fill the wave, and the s
-// partial sums of each i are added at the end. FP32: U = 8 above 64
+// partial sums of each i are added at the end. FP32: U = 8 above 32
 // particles, else 4; FP64: U = 2; U = 1 for an item with a single particle.
 //
 // Staging. Per batch of 64 stencil rows each lane resolves one row into at
@@ -546,7 +546,7 @@ k_pairs(PairArgs<T> A) {
     pair_item<T, 1, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
   else if (sizeof(T) == 8)
     pair_item<T, 2, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
-  else if (ni <= 64 || VJP)
+  else if (ni <= 32 || VJP)
     pair_item<T, 4, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
   else
     pair_item<T, 8, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
