@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 step timing")
     ap.add_argument("--cpu-sample", type=int, default=20000,
                     help="particles whose short-range force the CPU oracle evaluates")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the force timing and error legs of the 32^3 and 256^3 workloads")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward timing of the differentiable leapfrog")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -185,6 +187,48 @@ def powerspec_leg(binding, torch, w, pos, calls=20):
             "sigma_8cells": float(sig)}
 
 
+def config_leg(binding, torch, name, precisions=("fp32", "fp64"), calls=5, n_targets=512):
+    """One force evaluation of a named workload per precision: time (HIP
+    events, median-free mean over `calls` after one warm-up), particles/s,
+    pair interactions/s, and the RMS / max per-particle force error against
+    the oracle (O-PP at sampled particles + O-PM) on `n_targets` particles."""
+    from oracle import metrics
+    from oracle import pm as o_pm
+    from oracle import pp as o_pp
+    from paper_1510_07621_amd import ics
+    w = ics.workload(name)
+    pos = w.positions()
+    tg = np.sort(np.random.default_rng(99).choice(w.n, size=min(n_targets, w.n),
+                                                  replace=False))
+    ref = (o_pp.pp_accel(pos, w.mass, w.box, w.r_s, w.r_c, w.softening, w.G, targets=tg) +
+           o_pm.pm_accel(pos, w.mass, w.box, w.grid_n, w.r_s, w.G, targets=tg)) * w.mass
+    x = torch.as_tensor(pos, device="cuda").contiguous()
+    out = {"workload": name, "n_particles": w.n, "grid_n": w.grid_n}
+    for prec in precisions:
+        P = binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
+                                        cutoff_rs=w.cutoff_rs, softening=w.softening,
+                                        G=w.G, precision=prec), w.n)
+        F = P.force(x, w.mass)
+        pairs = P.pair_count(x)
+        P.set_timing(calls)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(calls):
+            P.force(x, w.mass, out=F)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / calls
+        ncall, st = P.stage_times()
+        err = metrics.force_errors(F.cpu().numpy()[:, tg], ref)
+        P.close()
+        out[prec] = {"ms_per_force": ms, "particles_per_s": w.n / (ms * 1e-3),
+                     "pairs": pairs, "pair_ms": st["pp"] / ncall,
+                     "pair_interactions_per_s": pairs / (st["pp"] / ncall * 1e-3),
+                     "force_err_rms": err["rms"], "force_err_max": err["max"]}
+    return out
+
+
 def ewald_leg(binding, torch, calls=5):
     """All-pairs PP force with the tabulated Ewald correction (64^3 table) on
     the 32^3 uniform workload, FP64: time per call and ordered pairs/s."""
@@ -312,6 +356,9 @@ def main():
             "pp_frac_of_fp64_peak": r64["pairs"] * FLOP_PER_PAIR / (pp64 * 1e-3) / 1e12
                                     / FP64_PEAK_TFLOPS,
         }
+    if not args.no_configs:
+        out["configs"] = [config_leg(binding, torch, "uniform32"),
+                          config_leg(binding, torch, "plummer256")]
     out["powerspec"] = powerspec_leg(binding, torch, w, pos)
     out["pp_ewald"] = ewald_leg(binding, torch)
     if not args.no_adjoint:

@@ -47,15 +47,22 @@ int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out,
 int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32_t cap,
                         double* map_out);
 
-/* FP64 table of the same split factor f, over r: [0, r_c) is cut into B equal
- * bins; with x = r B / r_c, k = floor(x), tau = 2 (x - k) - 1 in [-1, 1),
+/* FP64 table of the same split factor f: the variable v is chosen as for the
+ * FP32 table, but the softened distance is kept whenever only up to 8
+ * leading bins (next to the kink at r = 0, with r / (2 r_s) <= 0.9) miss
+ * twice the accuracy of the table over r (at least 4e-16); the pair sum
+ * evaluates those bins with a power series of f. [v0, v1] is cut into B equal
+ * bins; with x = (v - v0) B / (v1 - v0), k = floor(x), tau = 2 (x - k) - 1,
  * f = sum_{l=0..6} c_l[k] tau^l, the degree-6 polynomial through f at the
- * seven Chebyshev points of bin k (fitted in extended precision; within
- * 2e-15 of f for cutoff_rs <= 4.5, 2e-14 at 6); entry B is the constant f(r_c). Layout:
- * out[l * (B + 1) + k], l = 0..6, k = 0..B. Returns B and writes the 7 (B + 1)
- * doubles when cap >= 7 (B + 1) (out may be NULL with cap == 0). P3M_EINVAL (-1) for cutoff_rs <= 0 or non-finite, or
- * cap > 0 with NULL out. */
-int32_t p3m_split_table64(double cutoff_rs, double* out, int32_t cap);
+ * seven Chebyshev points of bin k (fitted in extended precision); entry B is
+ * the constant f at v1. Layout: out[l * (B + 1) + k], l = 0..6, k = 0..B;
+ * map_out (may be NULL) receives {variable (0: r, 1: softened distance), v0,
+ * v1, exact bins}. Returns B and writes the 7 (B + 1) doubles and the map
+ * when cap >= 7 (B + 1) (out may be NULL with cap == 0). P3M_EINVAL (-1) for
+ * cutoff_rs <= 0, softening_rs < 0, a non-finite argument, or cap > 0 with
+ * NULL out. */
+int32_t p3m_split_table64(double cutoff_rs, double softening_rs, double* out, int32_t cap,
+                          double* map_out);
 
 /* Edge, in cells, of the i-groups the pair sum uses for n particles on a
  * grid of grid_n^3 cells: the power of two (1, 2 or 4) closest to a mean of

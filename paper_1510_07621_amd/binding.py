@@ -78,7 +78,7 @@ def _load():
         "p3m_group_edge": (i32, [i64, i32]),
         "p3m_split_table": (i32, [dbl, dbl, ctypes.POINTER(ctypes.c_float), i32,
                                   ctypes.POINTER(dbl)]),
-        "p3m_split_table64": (i32, [dbl, ctypes.POINTER(dbl), i32]),
+        "p3m_split_table64": (i32, [dbl, dbl, ctypes.POINTER(dbl), i32, ctypes.POINTER(dbl)]),
         "p3m_cosmo_age": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
                                          ctypes.POINTER(dbl)]),
         "p3m_cosmo_scale_factor": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl,
@@ -164,15 +164,19 @@ def split_table(cutoff_rs: float, softening_rs: float = 0.0):
     return tab, (int(m[0]), float(m[1]), float(m[2]))
 
 
-def split_table64(cutoff_rs: float):
-    """FP64 split-factor table of the pair sum: a (7, B + 1) float64 array,
-    row l the coefficient of tau^l of each bin of r in [0, r_c)."""
+def split_table64(cutoff_rs: float, softening_rs: float = 0.0):
+    """FP64 split-factor table of the pair sum: a (7, B + 1) float64 array, row
+    l the coefficient of tau^l of each bin, and the map (variable, v0, v1,
+    exact bins) as for split_table plus the leading bins evaluated exactly."""
     import numpy as np
-    b = _lib.p3m_split_table64(cutoff_rs, None, 0)
+    b = _lib.p3m_split_table64(cutoff_rs, softening_rs, None, 0, None)
     _check(min(b, 0), "p3m_split_table64")
     buf = (ctypes.c_double * (7 * (b + 1)))()
-    _check(min(_lib.p3m_split_table64(cutoff_rs, buf, 7 * (b + 1)), 0), "p3m_split_table64")
-    return np.frombuffer(buf, dtype=np.float64).reshape(7, b + 1).copy()
+    m = (ctypes.c_double * 4)()
+    _check(min(_lib.p3m_split_table64(cutoff_rs, softening_rs, buf, 7 * (b + 1), m), 0),
+           "p3m_split_table64")
+    tab = np.frombuffer(buf, dtype=np.float64).reshape(7, b + 1).copy()
+    return tab, (int(m[0]), float(m[1]), float(m[2]), int(m[3]))
 
 
 @dataclass(frozen=True)

@@ -271,9 +271,9 @@ SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out) {
   const double kFitBound = 1e-7;
   double c[4 * kSplitBins];
   bins = std::min(bins, kSplitBins);
-  SplitMap m{1, soft_rs * (1.0 - 1e-6), std::sqrt(cutoff_rs * cutoff_rs + soft_rs * soft_rs)};
+  SplitMap m{1, soft_rs * (1.0 - 1e-6), std::sqrt(cutoff_rs * cutoff_rs + soft_rs * soft_rs), 0};
   if (fit_table(m.var, soft_rs, m.v0, m.v1, bins, c) > kFitBound) {
-    m = SplitMap{0, 0.0, cutoff_rs};
+    m = SplitMap{0, 0.0, cutoff_rs, 0};
     fit_table(m.var, soft_rs, m.v0, m.v1, bins, c);
   }
   const int stride = bins + 1;
@@ -285,24 +285,32 @@ SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out) {
   return m;
 }
 
-void split_table64(double cutoff_rs, double* out) {
-  // Piece k covers u = (k + t) u_c / B, t in [0, 1]; with tau = 2t - 1 the
-  // degree-6 polynomial through f at the seven Chebyshev points of [-1, 1],
-  // solved in extended precision so that only the final rounding to double
-  // remains (the pieces are narrow, so the coefficients fall off fast).
+// One set of degree-6 pieces of g over [v0, v1] in extended precision:
+// piece k covers v = v0 + (k + t)(v1 - v0)/B, t in [0, 1]; with tau = 2t - 1
+// the polynomial through g at the seven Chebyshev points of [-1, 1] (the
+// pieces are narrow, so the coefficients fall off fast and only the final
+// rounding to double remains). err[k]: the largest deviation from g of the
+// rounded piece on a dense sample.
+static void fit_table64(int var, long double e, long double v0, long double v1, double* out,
+                        long double* err) {
   typedef long double LD;
   const int B = kSplitBins, C = kSplitCoef64, stride = B + 1;
   const LD kPi = 3.14159265358979323846264338327950288L;
-  const LD u_c = 0.5L * (LD)cutoff_rs;
   auto f = [](LD u) { return std::erfc(u) + 1.12837916709551257389615890312154517L * u *
                                                 std::exp(-u * u); };
+  auto g = [&](LD v) {
+    if (var == 0) return f(0.5L * v);
+    LD r2 = v * v - e * e;
+    return f(0.5L * std::sqrt(r2 > 0 ? r2 : 0.0L));
+  };
+  const LD w = (v1 - v0) / B;
   for (int k = 0; k < B; ++k) {
     LD V[kSplitCoef64][kSplitCoef64 + 1];
     for (int j = 0; j < C; ++j) {
       LD tau = std::cos((2 * j + 1) * kPi / (2 * C));
       LD p = 1.0L;
       for (int l = 0; l < C; ++l, p *= tau) V[j][l] = p;
-      V[j][C] = f(u_c * ((LD)k + 0.5L * (tau + 1.0L)) / B);
+      V[j][C] = g(v0 + w * ((LD)k + 0.5L * (tau + 1.0L)));
     }
     for (int col = 0; col < C; ++col) {     // Gauss-Jordan, partial pivoting
       int piv = col;
@@ -316,9 +324,39 @@ void split_table64(double cutoff_rs, double* out) {
       }
     }
     for (int l = 0; l < C; ++l) out[l * stride + k] = (double)(V[l][C] / V[l][l]);
+    err[k] = 0;
+    for (int j = 0; j <= 32; ++j) {
+      LD tau = -1.0L + j / 16.0L, p = 0;
+      for (int l = C - 1; l >= 0; --l) p = p * tau + (LD)out[l * stride + k];
+      err[k] = std::max(err[k], std::fabs(p - g(v0 + w * ((LD)k + 0.5L * (tau + 1.0L)))));
+    }
   }
-  out[B] = (double)f(u_c);
+  out[B] = (double)g(v1);
   for (int l = 1; l < C; ++l) out[l * stride + B] = 0.0;
+}
+
+SplitMap split_table64(double cutoff_rs, double soft_rs, double* out) {
+  // Softened distance as the variable when the pieces that miss the accuracy
+  // of the r table (twice its worst piece, at least 4e-16) are only a few
+  // leading ones next to the kink at r = 0: those pairs, closer than a few
+  // bins, take a series of f in the kernel. Else r.
+  const int kMaxExact = 8;
+  long double err[kSplitBins];
+  const long double e = soft_rs;
+  fit_table64(0, e, 0.0L, cutoff_rs, out, err);
+  long double bound = 4e-16L;
+  for (int k = 0; k < kSplitBins; ++k) bound = std::max(bound, 2.0L * err[k]);
+  SplitMap m{1, soft_rs * (1.0 - 1e-9), std::sqrt(cutoff_rs * cutoff_rs + soft_rs * soft_rs), 0};
+  fit_table64(1, e, m.v0, m.v1, out, err);
+  for (int k = 0; k < kSplitBins; ++k)
+    if (err[k] > bound) m.exact = k + 1;
+  // the kernel's series for the exact pieces holds for u = r / (2 r_s) <= 0.9
+  const double u_top = 0.5 * (m.v0 + m.exact * (m.v1 - m.v0) / kSplitBins);
+  if (m.exact > kMaxExact || u_top > 0.9) {
+    m = SplitMap{0, 0.0, cutoff_rs, 0};
+    fit_table64(0, e, m.v0, m.v1, out, err);
+  }
+  return m;
 }
 
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
@@ -380,10 +418,20 @@ int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32
   return kSplitBins;
 }
 
-int32_t p3m_split_table64(double cutoff_rs, double* out, int32_t cap) {
-  if (!(cutoff_rs > 0) || !std::isfinite(cutoff_rs) || cap < 0 || (cap > 0 && !out))
+int32_t p3m_split_table64(double cutoff_rs, double softening_rs, double* out, int32_t cap,
+                          double* map_out) {
+  if (!(cutoff_rs > 0) || !std::isfinite(cutoff_rs) || !(softening_rs >= 0) ||
+      !std::isfinite(softening_rs) || cap < 0 || (cap > 0 && !out))
     return P3M_EINVAL;
-  if (cap >= kSplitCoef64 * (kSplitBins + 1)) p3m::split_table64(cutoff_rs, out);
+  if (cap >= kSplitCoef64 * (kSplitBins + 1)) {
+    p3m::SplitMap m = p3m::split_table64(cutoff_rs, softening_rs, out);
+    if (map_out) {
+      map_out[0] = m.var;
+      map_out[1] = m.v0;
+      map_out[2] = m.v1;
+      map_out[3] = m.exact;
+    }
+  }
   return kSplitBins;
 }
 
@@ -516,7 +564,11 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   }
   if (err == hipSuccess) {
     double tab64[kSplitCoef64 * (kSplitBins + 1)];
-    split_table64(q.cutoff_rs, tab64);
+    SplitMap m = split_table64(q.cutoff_rs, q.softening / r_s, tab64);
+    P->tab64_var = m.var;
+    P->tab64_v0 = m.v0 * r_s;
+    P->tab64_v1 = m.v1 * r_s;
+    P->tab64_exact = m.exact;
     err = hipMemcpy(W.split_tab64, tab64, sizeof(tab64), hipMemcpyHostToDevice);
   }
   if (err == hipSuccess)

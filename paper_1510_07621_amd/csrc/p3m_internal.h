@@ -80,6 +80,9 @@ struct p3m_plan {
   int64_t max_items = 0;
   int tab_var = 0;              // FP32 split table: variable (0: r, 1: softened r)
   double tab_v0 = 0, tab_v1 = 0;  // and its range, as lengths
+  int tab64_var = 0;            // FP64 split table: the same, and the number of
+  double tab64_v0 = 0, tab64_v1 = 0;  // leading pieces evaluated exactly
+  int tab64_exact = 0;
   int scan_tmp_len = 0;
   p3m::Workspace ws;
   // stage timers: events [call][2 * stage + {0: start, 1: end}]
@@ -149,10 +152,12 @@ int stencil_rows(int g, double radius_cells, int32_t* out, int cap);
 struct SplitMap {
   int var;
   double v0, v1;
+  int exact;    // FP64: leading pieces the kernel replaces by the exact formula
 };
 SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out);
-// FP64 table over r in [0, r_c): out[l * (kSplitBins + 1) + k] is the
-// coefficient of tau^l (tau = 2t - 1) of piece k; entry kSplitBins = f(r_c).
-void split_table64(double cutoff_rs, double* out);
+// FP64 table: out[l * (kSplitBins + 1) + k] is the coefficient of tau^l
+// (tau = 2t - 1) of piece k of the same variable choice; entry kSplitBins is
+// the constant value at v1.
+SplitMap split_table64(double cutoff_rs, double soft_rs, double* out);
 
 }  // namespace p3m

@@ -32,9 +32,10 @@
 // sqrt(r^2 + eps^2), which rsq already yields, so a pair costs a single
 // transcendental; when eps is too large against a piece for the cubic to
 // follow the kink at r = 0, the plan tabulates over r and a square root is
-// added. FP64: the device library's sqrt and rsqrt, and f from 64 pieces of
-// degree 6 over r in [0, r_c) (fitted in extended precision at the Chebyshev
-// points of each piece; error at FP64 rounding).
+// added. FP64: the device library's rsqrt, and f from 64 pieces of degree 6
+// (fitted in extended precision at the Chebyshev points of each piece; error
+// at FP64 rounding) over the softened distance as well, with the few pieces
+// next to the kink evaluated exactly; or over r, with a square root.
 #include <algorithm>
 
 #include "p3m_internal.h"
@@ -72,7 +73,8 @@ struct PairArgs {
   // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
   const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
-  double tab_s64;                       // FP64 table: kSplitBins / r_c
+  double tab_s64, tab_off64;            // FP64 table: x = s v - s v0 (v = r or rho)
+  int tab_exact;                        // FP64: leading pieces evaluated exactly
   double wscale;                        // -G, times s^3 on the FP32 path
   // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
   // pair Hessian (see pair_vjp_weights)
@@ -100,11 +102,37 @@ template <> struct SplitTable<double> {
   double c[kCoef][kTabStride];
 };
 
-// FP64 split factor f(r) from the table over x = r kSplitBins / r_c.
-__device__ __forceinline__ double split_f64(double r2, const PairArgs<double>& A,
+// f near r = 0 from its series: df/du = -(4/sqrt(pi)) u^2 e^{-u^2}, so
+// f = 1 - (4/sqrt(pi)) u^3 sum_n (-1)^n u^{2n} / (n! (2n + 3)), alternating with
+// falling terms for u < 1: 16 terms leave less than 4e-17 for u <= 0.9.
+constexpr int kSeriesTerms = 16;
+constexpr double series_coef(int n) {
+  double fact = 1.0;
+  for (int i = 2; i <= n; ++i) fact *= i;
+  return (n % 2 ? -1.0 : 1.0) / (fact * (2 * n + 3));
+}
+
+__device__ __forceinline__ double split_f64_series(double r2, double inv2rs) {
+  const double s = r2 * inv2rs * inv2rs;              // u^2
+  double p = series_coef(kSeriesTerms - 1);
+#pragma unroll
+  for (int n = kSeriesTerms - 2; n >= 0; --n) p = fma(p, s, series_coef(n));
+  return 1.0 - 2.2567583341910251 * (sqrt(r2) * inv2rs) * s * p;
+}
+
+// FP64 split factor f from the table. TAB 1: the variable is the softened
+// distance rho = q rsqrt(q), q = r^2 + eps^2 (no square root); the few
+// leading pieces next to the kink at r = 0 that a polynomial cannot follow to
+// FP64 rounding take the series above instead (pairs closer than a few bins,
+// u <= 0.9 by the plan's choice: rare, so the divergent branch is cheap).
+// TAB 0: the variable is r.
+template <int TAB>
+__device__ __forceinline__ double split_f64(double r2, double q, double inv,
+                                            const PairArgs<double>& A,
                                             const SplitTable<double>& tab) {
-  const double x = sqrt(r2) * A.tab_s64;
-  const int k = (int)x;                 // <= kSplitBins since r < r_c
+  const double x = TAB ? fma(q * inv, A.tab_s64, -A.tab_off64) : sqrt(r2) * A.tab_s64;
+  const int k = min(max((int)x, 0), kSplitBins);   // x >= 0 and k <= kSplitBins for r < r_c
+  if (TAB && k < A.tab_exact) return split_f64_series(r2, A.inv2rs);
   const double tau = 2.0 * (x - (double)k) - 1.0;
   double f = tab.c[kSplitCoef64 - 1][k];
 #pragma unroll
@@ -134,8 +162,9 @@ __device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
 template <int TAB>
 __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>& A,
                                               const SplitTable<double>& tab) {
-  const double inv = rsqrt(r2 + A.eps2);
-  const double f = split_f64(r2, A, tab);
+  const double q = r2 + A.eps2;
+  const double inv = rsqrt(q);
+  const double f = split_f64<TAB>(r2, q, inv, A, tab);
   return r2 > 0.0 ? f * (inv * inv * inv) : 0.0;   // eps may be 0
 }
 
@@ -166,11 +195,12 @@ template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<double>& A,
                                                  const SplitTable<double>& tab, double& w1,
                                                  double& w2) {
-  const double inv = rsqrt(r2 + A.eps2);
+  const double q = r2 + A.eps2;
+  const double inv = rsqrt(q);
   const double r = sqrt(r2);
   const double u = r * A.inv2rs;
   const double e = exp(-u * u);
-  const double f = split_f64(r2, A, tab);
+  const double f = split_f64<TAB>(r2, q, inv, A, tab);
   const double inv3 = inv * inv * inv;
   const bool pos = r2 > 0.0;                      // eps may be 0
   w1 = pos ? f * inv3 : 0.0;
@@ -578,8 +608,11 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.inv2rs = (T)(1.0 / (2.0 * P->r_s));
   A.wscale = -P->prm.G;
   if constexpr (sizeof(T) == 8) {
+    const double s = kSplitBins / (P->tab64_v1 - P->tab64_v0);
     A.split_tab = W.split_tab64;
-    A.tab_s64 = kSplitBins / P->r_c;
+    A.tab_s64 = s;
+    A.tab_off64 = s * P->tab64_v0;
+    A.tab_exact = P->tab64_exact;
   }
   if constexpr (sizeof(T) == 4) {
     const double s = kSplitBins / (P->tab_v1 - P->tab_v0);
@@ -610,14 +643,12 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
   A.force = force_out;
   A.force_fp32 = force_fp32;
   const unsigned grid = pair_grid(P);
-  if constexpr (sizeof(T) == 4) {
-    if (P->tab_var == 1) {            // split table over the softened distance
-      if (uniform_mass)
-        k_pairs<T, false, true, 1><<<grid, 64, 0, P->stream>>>(A);
-      else
-        k_pairs<T, false, false, 1><<<grid, 64, 0, P->stream>>>(A);
-      return hipGetLastError();
-    }
+  if ((sizeof(T) == 4 ? P->tab_var : P->tab64_var) == 1) {   // table over the softened distance
+    if (uniform_mass)
+      k_pairs<T, false, true, 1><<<grid, 64, 0, P->stream>>>(A);
+    else
+      k_pairs<T, false, false, 1><<<grid, 64, 0, P->stream>>>(A);
+    return hipGetLastError();
   }
   if (uniform_mass)
     k_pairs<T, false, true, 0><<<grid, 64, 0, P->stream>>>(A);
@@ -635,14 +666,12 @@ hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar
   A.force = pos_bar;
   A.force_fp32 = 0;
   const unsigned grid = pair_grid(P);
-  if constexpr (sizeof(T) == 4) {
-    if (P->tab_var == 1) {
-      if (uniform_mass)
-        k_pairs<T, false, true, 1, true><<<grid, 64, 0, P->stream>>>(A);
-      else
-        k_pairs<T, false, false, 1, true><<<grid, 64, 0, P->stream>>>(A);
-      return hipGetLastError();
-    }
+  if ((sizeof(T) == 4 ? P->tab_var : P->tab64_var) == 1) {
+    if (uniform_mass)
+      k_pairs<T, false, true, 1, true><<<grid, 64, 0, P->stream>>>(A);
+    else
+      k_pairs<T, false, false, 1, true><<<grid, 64, 0, P->stream>>>(A);
+    return hipGetLastError();
   }
   if (uniform_mass)
     k_pairs<T, false, true, 0, true><<<grid, 64, 0, P->stream>>>(A);

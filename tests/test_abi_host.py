@@ -218,26 +218,36 @@ def test_split_table_matches_erfc_split(b, cutoff_rs, soft_rs, var):
     assert np.max(np.abs(ends - tab[0][1:])) < 2e-7
 
 
-@pytest.mark.parametrize("cutoff_rs", [4.5, 3.0, 6.0])
-def test_split_table64_matches_erfc_split(b, cutoff_rs):
-    """The FP64 table (degree-6 pieces over r) agrees with SciPy's erfc-based f
-    over all of [0, r_c): to 2e-15 at the default cutoff, 2e-14 at 6 r_s."""
+@pytest.mark.parametrize("cutoff_rs,soft_rs,var", [
+    (4.5, 0.0, 1), (4.5, 0.024, 1), (3.0, 0.024, 1), (6.0, 0.01, 1),
+    (4.5, 0.24, 1), (4.5, 0.8, 0)])
+def test_split_table64_matches_erfc_split(b, cutoff_rs, soft_rs, var):
+    """The FP64 table, looked up as the kernel does (bins below `exact` by the
+    exact formula), agrees with SciPy's erfc-based f over all of [0, r_c):
+    3e-15 for cutoffs up to 4.5 r_s, 3e-14 at 6 (degree-6 pieces); the exact
+    bins are few and lie next to r = 0."""
     import numpy as np
-    tab = b.split_table64(cutoff_rs)
+    tab, (v, v0, v1, exact) = b.split_table64(cutoff_rs, soft_rs)
     B = tab.shape[1] - 1
+    assert tab.shape == (7, B + 1) and v == var and 0 <= exact <= 8
     r = np.linspace(0.0, cutoff_rs, 300001)[:-1]            # units of r_s
-    x = r * (B / cutoff_rs)
-    k = x.astype(np.int64)
+    vv = np.sqrt(r * r + soft_rs * soft_rs) if v == 1 else r
+    x = (vv - v0) * (B / (v1 - v0))
+    assert x.min() >= 0
+    k = np.minimum(x.astype(np.int64), B)
     tau = 2.0 * (x - k) - 1.0
-    assert tab.shape == (7, B + 1)
     f = tab[6][k]
     for l in range(5, -1, -1):
         f = f * tau + tab[l][k]
-    assert np.max(np.abs(f - _split_f(0.5 * r))) < (2e-15 if cutoff_rs <= 4.5 else 2e-14)
+    f = np.where(k < exact, _split_f(0.5 * r), f)
+    assert np.max(np.abs(f - _split_f(0.5 * r))) < (3e-15 if cutoff_rs <= 4.5 else 3e-14)
+    if soft_rs == 0.0:
+        assert exact == 0                     # no kink: the table covers everything
     assert tab[0][B] == pytest.approx(_split_f(0.5 * cutoff_rs), rel=1e-15)
     assert np.all(tab[1:, B] == 0)
-    assert b._lib.p3m_split_table64(0.0, None, 0) == -1
-    assert b._lib.p3m_split_table64(4.5, None, 3) == -1
+    assert b._lib.p3m_split_table64(0.0, 0.0, None, 0, None) == -1
+    assert b._lib.p3m_split_table64(4.5, -1.0, None, 0, None) == -1
+    assert b._lib.p3m_split_table64(4.5, 0.0, None, 3, None) == -1
 
 
 def test_split_table_rejects_bad_arguments(b):
