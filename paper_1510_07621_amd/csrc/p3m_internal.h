@@ -21,7 +21,7 @@ template <> struct Vec<double> {
   using v4 = double4;
 };
 
-constexpr int kPairCap = 256;     // j-particles staged in LDS per pass of the pair loop
+constexpr int kPairCap = 128;     // j-particles staged in LDS per pass of the pair loop
 constexpr int kBrick = 8;         // cells per brick edge (deposit, interpolation)
 constexpr int kChunk = 64;        // i-particles per pair-loop work item (one wavefront)
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)

@@ -20,8 +20,7 @@
 // Staging. Per batch of 64 stencil rows each lane resolves one row into at
 // most three contiguous sorted runs (the z-run split where it crosses the
 // periodic box face), a wave scan flattens them, and the wave stages the
-// runs' particles into LDS (kPairCap at a time in FP32, half that in FP64) as
-// positions relative to the
+// runs' particles into LDS (kPairCap at a time) as positions relative to the
 // group's first cell, carrying the periodic shift of the run. Positions are
 // rebuilt from cell-relative offsets and small integer cell differences, so
 // the FP32 path never subtracts two large coordinates.
@@ -44,13 +43,17 @@ namespace p3m {
 namespace {
 
 constexpr int kDesc = 3 * 64;          // runs per batch of 64 rows
-// j-particles staged in LDS per pass: kPairCap in FP32; half as many in FP64,
-// so that the workgroup's LDS stays under 1/12 of a CU's (3 waves per SIMD,
-// which its registers allow).
+// j-particles staged in LDS per pass (kPairCap), small enough that the
+// workgroup's LDS stays under 1/20 of a CU's in FP32 (5 waves per SIMD, with
+// registers capped to match) and under 1/12 in FP64 (3 waves, as its
+// registers allow).
 template <typename T> struct Stage {
-  static constexpr int kCap = sizeof(T) == 4 ? kPairCap : kPairCap / 2;
+  static constexpr int kCap = kPairCap;
   static constexpr int kPer = kCap / 64;   // consecutive staged entries per lane
 };
+// Waves per SIMD the compiler must leave room for (caps the registers).
+template <typename T, bool VJP>
+constexpr int kPairWaves = sizeof(T) == 4 && !VJP ? 5 : 1;
 // A coordinate far outside any box: its squared separation from any real
 // particle is ~1e37, finite in FP32 and far beyond every cutoff.
 constexpr float kFar = 1e18f;
@@ -313,12 +316,10 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   }
   int npairs = 0;
 
-  // Stencil rows are resolved 64 at a time (one per lane); the next batch's
-  // start[] lookups are issued before the current batch's pair loop so their
-  // latency hides behind it.
-  RowRuns<T> nxt = resolve_rows<T>(A, 0, lane, gx0, gy0, gz0);
+  // Stencil rows are resolved 64 at a time (one per lane). (Fetching the next
+  // batch's start[] entries ahead measured no faster and costs registers.)
   for (int rb = 0; rb < A.nrows; rb += 64) {
-    const RowRuns<T> cur = nxt;
+    const RowRuns<T> cur = resolve_rows<T>(A, rb, lane, gx0, gy0, gz0);
     __syncthreads();       // previous batch is done with the descriptors and jb
     const int tot_l = cur.cnt[0] + cur.cnt[1] + cur.cnt[2];
     const int inc = wave_inclusive(tot_l);
@@ -338,8 +339,6 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
     S.d_ry[lane] = cur.ry;
     const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
     if (lane == 63) S.d_pre[kDesc] = total;
-    if (total == 0 && rb + 64 < A.nrows)          // empty batch: nothing to overlap with
-      nxt = resolve_rows<T>(A, rb + 64, lane, gx0, gy0, gz0);
 
     for (int c0 = 0; c0 < total; c0 += kCap) {
       const int cn = min(kCap, total - c0);
@@ -415,8 +414,6 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
         far.w = T(0);
         S.jb[cn + lane] = far;
       }
-      if (c0 + kCap >= total && rb + 64 < A.nrows)
-        nxt = resolve_rows<T>(A, rb + 64, lane, gx0, gy0, gz0);   // in flight during the loop
       __syncthreads();
       // lane (set, stream) takes staged entries st, st + ns, ...; the trip
       // count is wave-uniform; reads past the end (at most ns - 1) hit the
@@ -532,7 +529,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
 }
 
 template <typename T, bool COUNT, bool UM, int TAB, bool VJP = false>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, (kPairWaves<T, VJP>))
 k_pairs(PairArgs<T> A) {
   __shared__ PairShared<T, VJP> S;
   const int lane = threadIdx.x;
