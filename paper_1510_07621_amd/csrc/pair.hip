@@ -48,12 +48,16 @@ constexpr int kDesc = 3 * 64;          // runs per batch of 64 rows
 // registers capped to match) and under 1/12 in FP64 (3 waves, as its
 // registers allow).
 template <typename T> struct Stage {
-  static constexpr int kCap = kPairCap;
+  static constexpr int kCap = sizeof(T) == 4 ? kPairCap : kPairCap / 2;
   static constexpr int kPer = kCap / 64;   // consecutive staged entries per lane
 };
+// At most kStreams streams, so kStreams far sentinels after the staged
+// entries cover every read past the end (an item with fewer than 64 / kStreams
+// slot sets leaves lanes idle; only items of a handful of particles).
+constexpr int kStreams = 16;
 // Waves per SIMD the compiler must leave room for (caps the registers).
 template <typename T, bool VJP>
-constexpr int kPairWaves = sizeof(T) == 4 && !VJP ? 5 : 1;
+constexpr int kPairWaves = VJP ? 1 : (sizeof(T) == 4 ? 5 : 4);
 // A coordinate far outside any box: its squared separation from any real
 // particle is ~1e37, finite in FP32 and far beyond every cutoff.
 constexpr float kFar = 1e18f;
@@ -224,9 +228,9 @@ template <typename T, bool VJP>
 struct PairShared {
   SplitTable<T> tab;                       // first, so one address register reaches
                                            // all coefficient arrays
-  typename Vec<T>::v4 jb[Stage<T>::kCap + 64];   // staged j (+ far sentinels); reused for
+  typename Vec<T>::v4 jb[Stage<T>::kCap + kStreams];   // staged j (+ far sentinels); reused for
                                                 // the reduction
-  typename Vec<T>::v4 jl[VJP ? Stage<T>::kCap + 64 : 1];   // adjoint mode: staged j cotangents
+  typename Vec<T>::v4 jl[VJP ? Stage<T>::kCap + kStreams : 1];   // adjoint mode: staged j cotangents
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
   int owner[Stage<T>::kCap];               // run of each staged entry of a chunk
   int d_rx[64], d_ry[64];                  // x, y cell offsets of each row
@@ -286,7 +290,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
   const T h = A.h;
   const int nu = (ni + U - 1) / U;      // slot sets
-  const int ns = 64 / nu;               // streams
+  const int ns = min(64 / nu, kStreams);  // streams
   const int il = lane % nu, st = lane / nu;
   const bool active = st < ns;
 
@@ -412,7 +416,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
         T4 far;
         far.x = far.y = far.z = T(-kFar);
         far.w = T(0);
-        S.jb[cn + lane] = far;
+        if (lane < kStreams) S.jb[cn + lane] = far;
       }
       __syncthreads();
       // lane (set, stream) takes staged entries st, st + ns, ...; the trip
