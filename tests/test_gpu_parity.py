@@ -267,7 +267,7 @@ def test_permutation_invariance():
 
 @pytest.mark.parametrize("name,precision,tol", [
     ("zeldovich128", "fp32", 1e-3), ("zeldovich128", "fp64", 1e-6),
-    ("plummer256", "fp32", 1e-3)])
+    ("plummer256", "fp32", 1e-3), ("plummer256", "fp64", 1e-6)])
 def test_full_size_sampled_parity(name, precision, tol):
     w = ics.workload(name)
     pos = workload_positions(name)
