@@ -43,12 +43,13 @@ namespace p3m {
 namespace {
 
 constexpr int kDesc = 3 * 64;          // runs per batch of 64 rows
-// j-particles staged in LDS per pass (kPairCap), small enough that the
-// workgroup's LDS stays under 1/20 of a CU's in FP32 (5 waves per SIMD, with
-// registers capped to match) and under 1/12 in FP64 (3 waves, as its
-// registers allow).
-template <typename T> struct Stage {
-  static constexpr int kCap = sizeof(T) == 4 ? kPairCap : kPairCap / 2;
+// j-particles staged in LDS per pass: kPairCap for the FP32 force, half that
+// for FP64 and for the adjoint (which stages the cotangents too), so that the
+// workgroup's LDS leaves room for the waves per SIMD that kPairWaves asks the
+// compiler to fit in registers (FP32 force 5, FP64 force 4, FP32 adjoint 4,
+// FP64 adjoint 3; measured best).
+template <typename T, bool VJP> struct Stage {
+  static constexpr int kCap = sizeof(T) == 4 && !VJP ? kPairCap : kPairCap / 2;
   static constexpr int kPer = kCap / 64;   // consecutive staged entries per lane
 };
 // At most kStreams streams, so kStreams far sentinels after the staged
@@ -57,7 +58,7 @@ template <typename T> struct Stage {
 constexpr int kStreams = 16;
 // Waves per SIMD the compiler must leave room for (caps the registers).
 template <typename T, bool VJP>
-constexpr int kPairWaves = VJP ? 1 : (sizeof(T) == 4 ? 5 : 4);
+constexpr int kPairWaves = sizeof(T) == 4 ? (VJP ? 4 : 5) : (VJP ? 3 : 4);
 // A coordinate far outside any box: its squared separation from any real
 // particle is ~1e37, finite in FP32 and far beyond every cutoff.
 constexpr float kFar = 1e18f;
@@ -228,11 +229,11 @@ template <typename T, bool VJP>
 struct PairShared {
   SplitTable<T> tab;                       // first, so one address register reaches
                                            // all coefficient arrays
-  typename Vec<T>::v4 jb[Stage<T>::kCap + kStreams];   // staged j (+ far sentinels); reused for
+  typename Vec<T>::v4 jb[Stage<T, VJP>::kCap + kStreams];   // staged j (+ far sentinels); reused for
                                                 // the reduction
-  typename Vec<T>::v4 jl[VJP ? Stage<T>::kCap + kStreams : 1];   // adjoint mode: staged j cotangents
+  typename Vec<T>::v4 jl[VJP ? Stage<T, VJP>::kCap + kStreams : 1];   // adjoint mode: staged j cotangents
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
-  int owner[Stage<T>::kCap];               // run of each staged entry of a chunk
+  int owner[Stage<T, VJP>::kCap];               // run of each staged entry of a chunk
   int d_rx[64], d_ry[64];                  // x, y cell offsets of each row
   int i_lo[16], i_pre[17];
 };
@@ -285,7 +286,7 @@ template <typename T, int U, bool COUNT, bool UM, int TAB, bool VJP>
 __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJP>& S, int gx0,
                                           int gy0, int gz0, int ibeg, int ni) {
   using T4 = typename Vec<T>::v4;
-  constexpr int kCap = Stage<T>::kCap, kStage = Stage<T>::kPer;
+  constexpr int kCap = Stage<T, VJP>::kCap, kStage = Stage<T, VJP>::kPer;
   const int lane = threadIdx.x;
   const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
   const T h = A.h;
