@@ -11,9 +11,8 @@
 //
 // the particle's effect on the density it deposits, and on its own
 // interpolation weights. The stages: sort lam into the particle order of the
-// sorted cell list; deposit Lam (three components, brick-local LDS
-// accumulation as in the mass deposit) and take its divergence S on the
-// nodes; solve psi = P S with the same FFT Poisson solve as the forward
+// sorted cell list; deposit Lam (three components, gathered per node like
+// the mass deposit) and take its divergence S on the nodes; solve psi = P S with the same FFT Poisson solve as the forward
 // potential; then, per brick, stage phi (with the gradient halo) and psi in
 // LDS and gather the weight gradients of each particle.
 //
@@ -38,58 +37,6 @@ k_lambda_sort(int64_t n, const int32_t* __restrict__ perm, const double* __restr
   o.z = (T)fbar[2 * n + i];
   o.w = T(0);
   lam[s] = o;
-}
-
-// Lam_d = sum_i m_i lam_{i,d} W(x_i - c), d = 0, 1, 2 (three grids).
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_deposit_lambda(const typename Vec<T>::v4* __restrict__ rec,
-                 const typename Vec<T>::v4* __restrict__ lam, const int32_t* __restrict__ skey,
-                 const int32_t* __restrict__ start, int ng, int lg, T inv_h,
-                 T* __restrict__ grids) {
-  constexpr int kN = kN1 * kN1 * kN1;
-  __shared__ T acc[3][kN];
-  __shared__ BrickRuns R;
-  const int lb = lg - 3;
-  const int b = blockIdx.x, mb = (1 << lb) - 1;
-  const int bz0 = (b & mb) * kBrick, by0 = ((b >> lb) & mb) * kBrick, bx0 = (b >> (2 * lb)) * kBrick;
-  for (int i = threadIdx.x; i < kN; i += kThreads) acc[0][i] = acc[1][i] = acc[2][i] = T(0);
-  load_runs(R, start, lg, bx0, by0, bz0);
-  const int total = R.pre[kRows];
-  for (int f = threadIdx.x; f < total; f += kThreads) {
-    int r = find_run(R, f);
-    int s = R.lo[r] + (f - R.pre[r]);
-    const typename Vec<T>::v4 p = rec[s];
-    const typename Vec<T>::v4 l = lam[s];
-    int lx = r / kBrick, ly = r % kBrick, lz = (skey[s] & (ng - 1)) - bz0;
-    T tx = p.x * inv_h, ty = p.y * inv_h, tz = p.z * inv_h;
-    T wx[2] = {T(1) - tx, tx}, wy[2] = {T(1) - ty, ty}, wz[2] = {T(1) - tz, tz};
-    const T v[3] = {p.w * l.x, p.w * l.y, p.w * l.z};
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          const T w = wx[a] * wy[c] * wz[d];
-          const int q = ((lx + a) * kN1 + (ly + c)) * kN1 + lz + d;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) atomicAdd(&acc[k][q], v[k] * w);
-        }
-  }
-  __syncthreads();
-  const int mask = ng - 1;
-  const int64_t ncell = (int64_t)1 << (3 * lg);
-  for (int i = threadIdx.x; i < kN; i += kThreads) {
-    int nx = i / (kN1 * kN1), ny = (i / kN1) % kN1, nz = i % kN1;
-    int64_t g = (((int64_t)((bx0 + nx) & mask) << lg | ((by0 + ny) & mask)) << lg) |
-                ((bz0 + nz) & mask);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const T v = acc[k][i];
-      if (v != T(0)) atomicAdd(&grids[k * ncell + g], v);
-    }
-  }
 }
 
 // S(c) = sum_d (D_d Lam_d)(c), D_d the central difference of the forward path.
@@ -228,14 +175,8 @@ hipError_t launch_lambda_sort(p3m_plan* P, int64_t n, const double* force_bar) {
 template <typename T>
 hipError_t launch_deposit_lambda(p3m_plan* P) {
   Workspace& W = P->ws;
-  hipError_t e = launch_fill_i32((int32_t*)W.lam_grid, 3 * P->ncell * (int64_t)(sizeof(T) / 4),
-                                 0, P->stream);
+  hipError_t e = launch_deposit3<T>(P, W.lam, W.lam_grid);
   if (e != hipSuccess) return e;
-  const int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
-  k_deposit_lambda<T><<<nb, kThreads, 0, P->stream>>>(
-      (const typename Vec<T>::v4*)W.rec, (const typename Vec<T>::v4*)W.lam, W.skey, W.start,
-      P->ng, P->lg, T(1.0 / P->h), (T*)W.lam_grid);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   T c1, c2;
   fd_coefficients(P, c1, c2);
   k_divergence<T><<<blocks_of(P->ncell, 256), 256, 0, P->stream>>>(

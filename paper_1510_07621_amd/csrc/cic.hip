@@ -6,10 +6,8 @@
 // each axis with weights 1 - t and t (nodes at c h, periodic), so a brick's
 // particles touch (kBrick + 1)^3 nodes.
 //
-// Deposit: the brick's particles are accumulated into an LDS copy of those
-// nodes with LDS atomics, then each non-zero node is added to the global grid
-// with one global atomic (only the brick faces overlap other bricks). The
-// density is rho = sum m W / h^3.
+// Deposit: each brick's 8^3 nodes gather the particles of the cells around
+// them (no atomics; see k_deposit_gather). The density is rho = sum m W / h^3.
 //
 // Interpolation: the brick's potential plus a two-node halo, (kBrick + 5)^3
 // values, is staged in LDS; the central-difference gradient (order 4:
@@ -25,45 +23,65 @@ namespace {
 
 using namespace brick;
 
-template <typename T>
+// Deposit by gathering: the workgroup owns the 8^3 nodes of its brick (every
+// grid node belongs to exactly one brick, so each is written once, with no
+// atomics and in a fixed order). Node n takes, per axis, weight t from the
+// particles of cell n - 1 (n is that cell's upper node) and 1 - t from those
+// of cell n, so the 8^3 nodes need the cells [-1, 8)^3 around the brick,
+// whose sorted ranges are staged in LDS first. NC = 1: mass, scaled by
+// 1 / h^3 (the density); NC = 3: mass times each component of a cotangent
+// (the adjoint's deposit), unscaled, to out[c * ng^3 + node].
+template <typename T, int NC>
 __global__ void __launch_bounds__(kThreads)
-k_deposit(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict__ skey,
-          const int32_t* __restrict__ start, int ng, int lg, T inv_h, T inv_h3,
-          T* __restrict__ grid) {
-  __shared__ T acc[kN1 * kN1 * kN1];
-  __shared__ BrickRuns R;
-  const int lb = lg - 3;                          // log2(ng / kBrick)
-  const int b = blockIdx.x, mb = (1 << lb) - 1;
+k_deposit_gather(const typename Vec<T>::v4* __restrict__ rec,
+                 const typename Vec<T>::v4* __restrict__ lam, const int32_t* __restrict__ start,
+                 int ng, int lg, T inv_h, T scale, T* __restrict__ out) {
+  constexpr int kC = kN1 * kN1 * kN1;             // cells [-1, kBrick)^3
+  __shared__ int cs[kC], cn[kC];
+  const int lb = lg - 3, mb = (1 << lb) - 1, mask = ng - 1;
+  const int b = blockIdx.x;
   const int bz0 = (b & mb) * kBrick, by0 = ((b >> lb) & mb) * kBrick, bx0 = (b >> (2 * lb)) * kBrick;
-  for (int i = threadIdx.x; i < kN1 * kN1 * kN1; i += kThreads) acc[i] = T(0);
-  load_runs(R, start, lg, bx0, by0, bz0);
-  const int total = R.pre[kRows];
-  for (int f = threadIdx.x; f < total; f += kThreads) {
-    int r = find_run(R, f);
-    int s = R.lo[r] + (f - R.pre[r]);
-    typename Vec<T>::v4 p = rec[s];
-    int lx = r / kBrick, ly = r % kBrick, lz = (skey[s] & (ng - 1)) - bz0;
-    T tx = p.x * inv_h, ty = p.y * inv_h, tz = p.z * inv_h;
-    T wx[2] = {T(1) - tx, tx}, wy[2] = {T(1) - ty, ty}, wz[2] = {T(1) - tz, tz};
+  for (int e = threadIdx.x; e < kC; e += kThreads) {
+    const int gx = (bx0 - 1 + e / (kN1 * kN1)) & mask, gy = (by0 - 1 + (e / kN1) % kN1) & mask,
+              gz = (bz0 - 1 + e % kN1) & mask;
+    const int64_t c = (((int64_t)gx << lg | gy) << lg) | gz;
+    const int lo = start[c];
+    cs[e] = lo;
+    cn[e] = start[c + 1] - lo;
+  }
+  __syncthreads();
+  const int64_t ncell = (int64_t)1 << (3 * lg);
+  for (int node = threadIdx.x; node < kBrick * kBrick * kBrick; node += kThreads) {
+    const int i = node >> 6, j = (node >> 3) & 7, k = node & 7;
+    T acc[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] = T(0);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        T mxy = p.w * wx[a] * wy[c];
-        int base = ((lx + a) * kN1 + (ly + c)) * kN1 + lz;
-        atomicAdd(&acc[base], mxy * wz[0]);
-        atomicAdd(&acc[base + 1], mxy * wz[1]);
-      }
-  }
-  __syncthreads();
-  const int mask = ng - 1;
-  for (int i = threadIdx.x; i < kN1 * kN1 * kN1; i += kThreads) {
-    T v = acc[i];
-    if (v != T(0)) {
-      int nx = i / (kN1 * kN1), ny = (i / kN1) % kN1, nz = i % kN1;
-      int gx = (bx0 + nx) & mask, gy = (by0 + ny) & mask, gz = (bz0 + nz) & mask;
-      atomicAdd(&grid[(((int64_t)gx << lg | gy) << lg) | gz], v * inv_h3);
-    }
+      for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int e = ((i + a) * kN1 + (j + bb)) * kN1 + (k + c);
+          const int s0 = cs[e], s1 = s0 + cn[e];
+          for (int s = s0; s < s1; ++s) {
+            const typename Vec<T>::v4 p = rec[s];
+            const T tx = p.x * inv_h, ty = p.y * inv_h, tz = p.z * inv_h;
+            const T w = (a ? T(1) - tx : tx) * (bb ? T(1) - ty : ty) * (c ? T(1) - tz : tz);
+            if constexpr (NC == 1) {
+              acc[0] += p.w * w;
+            } else {
+              const typename Vec<T>::v4 l = lam[s];
+              const T mw = p.w * w;
+              acc[0] += mw * l.x;
+              acc[1] += mw * l.y;
+              acc[2] += mw * l.z;
+            }
+          }
+        }
+    const int64_t g = (((int64_t)(bx0 + i) << lg | (by0 + j)) << lg) | (bz0 + k);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) out[q * ncell + g] = acc[q] * scale;
   }
 }
 
@@ -142,15 +160,20 @@ k_interp(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict_
 template <typename T>
 hipError_t launch_deposit(p3m_plan* P) {
   Workspace& W = P->ws;
-  hipError_t e = launch_fill_i32((int32_t*)W.grid, P->ncell * (int64_t)(sizeof(T) / 4), 0,
-                                 P->stream);
-  if (e != hipSuccess) return e;
-  int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
-  T inv_h = T(1.0 / P->h);
-  T inv_h3 = T(1.0 / (P->h * P->h * P->h));
-  k_deposit<T><<<nb, kThreads, 0, P->stream>>>((const typename Vec<T>::v4*)W.rec, W.skey,
-                                               W.start, P->ng, P->lg, inv_h, inv_h3,
-                                               (T*)W.grid);
+  const int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
+  k_deposit_gather<T, 1><<<nb, kThreads, 0, P->stream>>>(
+      (const typename Vec<T>::v4*)W.rec, nullptr, W.start, P->ng, P->lg, T(1.0 / P->h),
+      T(1.0 / (P->h * P->h * P->h)), (T*)W.grid);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_deposit3(p3m_plan* P, const void* lam, void* grids) {
+  Workspace& W = P->ws;
+  const int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
+  k_deposit_gather<T, 3><<<nb, kThreads, 0, P->stream>>>(
+      (const typename Vec<T>::v4*)W.rec, (const typename Vec<T>::v4*)lam, W.start, P->ng, P->lg,
+      T(1.0 / P->h), T(1), (T*)grids);
   return hipGetLastError();
 }
 
@@ -177,6 +200,8 @@ hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32
 
 template hipError_t launch_deposit<float>(p3m_plan*);
 template hipError_t launch_deposit<double>(p3m_plan*);
+template hipError_t launch_deposit3<float>(p3m_plan*, const void*, void*);
+template hipError_t launch_deposit3<double>(p3m_plan*, const void*, void*);
 template hipError_t launch_interp<float>(p3m_plan*, int64_t, void*, int);
 template hipError_t launch_interp<double>(p3m_plan*, int64_t, void*, int);
 

@@ -108,6 +108,8 @@ hipError_t launch_items(p3m_plan* P);
 template <typename T>
 hipError_t launch_deposit(p3m_plan* P);
 template <typename T>
+hipError_t launch_deposit3(p3m_plan* P, const void* lam, void* grids);   // m * lam, 3 grids
+template <typename T>
 hipError_t launch_fft_poisson(p3m_plan* P);
 template <typename T>
 hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32);
