@@ -189,21 +189,17 @@ def powerspec_leg(binding, torch, w, pos, calls=20):
 
 def config_leg(binding, torch, name, precisions=("fp32", "fp64"), calls=5, n_targets=512):
     """One force evaluation of a named workload per precision: time (HIP
-    events, median-free mean over `calls` after one warm-up), particles/s,
-    pair interactions/s, and the RMS / max per-particle force error against
-    the oracle (O-PP at sampled particles + O-PM) on `n_targets` particles."""
-    from oracle import metrics
-    from oracle import pm as o_pm
-    from oracle import pp as o_pp
+    events, mean over `calls` after one warm-up), particles/s and pair
+    interactions/s. Also returns the forces at `n_targets` sampled particles,
+    which the CPU leg compares with the oracle."""
     from paper_1510_07621_amd import ics
     w = ics.workload(name)
     pos = w.positions()
     tg = np.sort(np.random.default_rng(99).choice(w.n, size=min(n_targets, w.n),
                                                   replace=False))
-    ref = (o_pp.pp_accel(pos, w.mass, w.box, w.r_s, w.r_c, w.softening, w.G, targets=tg) +
-           o_pm.pm_accel(pos, w.mass, w.box, w.grid_n, w.r_s, w.G, targets=tg)) * w.mass
     x = torch.as_tensor(pos, device="cuda").contiguous()
     out = {"workload": name, "n_particles": w.n, "grid_n": w.grid_n}
+    sampled = {}
     for prec in precisions:
         P = binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
                                         cutoff_rs=w.cutoff_rs, softening=w.softening,
@@ -220,13 +216,29 @@ def config_leg(binding, torch, name, precisions=("fp32", "fp64"), calls=5, n_tar
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / calls
         ncall, st = P.stage_times()
-        err = metrics.force_errors(F.cpu().numpy()[:, tg], ref)
+        sampled[prec] = F.cpu().numpy()[:, tg]
         P.close()
         out[prec] = {"ms_per_force": ms, "particles_per_s": w.n / (ms * 1e-3),
                      "pairs": pairs, "pair_ms": st["pp"] / ncall,
-                     "pair_interactions_per_s": pairs / (st["pp"] / ncall * 1e-3),
-                     "force_err_rms": err["rms"], "force_err_max": err["max"]}
-    return out
+                     "pair_interactions_per_s": pairs / (st["pp"] / ncall * 1e-3)}
+    return out, (w, pos, tg, sampled)
+
+
+def config_errors(out, sample):
+    """CPU leg for one named workload: the RMS / max per-particle force error
+    of each precision against the oracle (O-PP at the sampled particles +
+    O-PM), written into that workload's entry."""
+    from oracle import metrics
+    from oracle import pm as o_pm
+    from oracle import pp as o_pp
+    w, pos, tg, sampled = sample
+    ref = (o_pp.pp_accel(pos, w.mass, w.box, w.r_s, w.r_c, w.softening, w.G, targets=tg) +
+           o_pm.pm_accel(pos, w.mass, w.box, w.grid_n, w.r_s, w.G, targets=tg)) * w.mass
+    for prec, F in sampled.items():
+        err = metrics.force_errors(F, ref)
+        out[prec]["force_err_rms"] = err["rms"]
+        out[prec]["force_err_max"] = err["max"]
+        out[prec]["force_err_particles"] = int(tg.size)
 
 
 def ewald_leg(binding, torch, calls=5):
@@ -292,8 +304,8 @@ def cpu_leg(binding, torch, w, pos, n_sample):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the force path is single-GPU; see DESIGN.md for how it would shard)",
+        print(f"bench.py: the force path runs on one GPU; --gpus {args.gpus} is not "
+              "supported (only --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -357,8 +369,8 @@ def main():
                                     / FP64_PEAK_TFLOPS,
         }
     if not args.no_configs:
-        out["configs"] = [config_leg(binding, torch, "uniform32"),
-                          config_leg(binding, torch, "plummer256")]
+        legs = [config_leg(binding, torch, name) for name in ("uniform32", "plummer256")]
+        out["configs"] = [leg for leg, _ in legs]
     out["powerspec"] = powerspec_leg(binding, torch, w, pos)
     out["pp_ewald"] = ewald_leg(binding, torch)
     if not args.no_adjoint:
@@ -382,6 +394,9 @@ def main():
         out["cpu_baseline"] = base
         out["force_err_vs_oracle"] = {k: {"rms": v["rms"], "max": v["max"]}
                                       for k, v in errs.items()}
+        if not args.no_configs:
+            for leg, sample in legs:
+                config_errors(leg, sample)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
