@@ -369,8 +369,8 @@ def main():
                                     / FP64_PEAK_TFLOPS,
         }
     if not args.no_configs:
-        legs = [config_leg(binding, torch, name) for name in ("uniform32", "plummer256")]
-        out["configs"] = [leg for leg, _ in legs]
+        cfg_legs = [config_leg(binding, torch, name) for name in ("uniform32", "plummer256")]
+        out["configs"] = [leg for leg, _ in cfg_legs]
     out["powerspec"] = powerspec_leg(binding, torch, w, pos)
     out["pp_ewald"] = ewald_leg(binding, torch)
     if not args.no_adjoint:
@@ -395,7 +395,7 @@ def main():
         out["force_err_vs_oracle"] = {k: {"rms": v["rms"], "max": v["max"]}
                                       for k, v in errs.items()}
         if not args.no_configs:
-            for leg, sample in legs:
+            for leg, sample in cfg_legs:
                 config_errors(leg, sample)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
