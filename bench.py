@@ -57,15 +57,16 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_zeldovich128_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_pairs_zeldovich128_valu.json")
 PAIR_SOURCE = os.path.join(ROOT, "paper_1510_07621_amd", "csrc", "pair.hip")
 
 
-def measured_traffic():
-    """HBM bytes per k_pairs launch from the committed counter summary, or
-    None when the pair kernel's source changed after the counters were taken."""
+def counter_record(path):
+    """A committed counter summary of k_pairs, or None when the pair kernel's
+    source changed after the counters were taken."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
         with open(PAIR_SOURCE, "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
@@ -73,7 +74,22 @@ def measured_traffic():
         return None
     if rec.get("pair_source_sha256") != digest:
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per k_pairs launch (FETCH_SIZE and WRITE_SIZE passes)."""
+    rec = counter_record(TRAFFIC_FILE)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def measured_valu():
+    """VALU issue and lane utilisation of k_pairs (SQ and GRBM counter pass)."""
+    rec = counter_record(VALU_FILE)
+    if not rec:
+        return None
+    return {k: rec[k] for k in ("valu_issue_util", "valu_lane_util", "valu_issue_per_cu_clock",
+                                "valu_issue_ceiling_per_cu_clock", "clock_ghz")}
 
 
 def run_steps(binding, plan, x, p, F, m, dt, box, steps):
@@ -351,6 +367,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": measured_traffic(),
+            "valu": measured_valu(),
             "flop_per_pair": FLOP_PER_PAIR,
             "avg_launch_ms": pp_ms,
         },

@@ -81,6 +81,7 @@ struct PairArgs {
   // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
   const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
+  float rho_e2, rho_cut2;               // tab_e2 / tab_s2 and r_c^2 + rho_e2
   double tab_s64, tab_off64;            // FP64 table: x = s v - s v0 (v = r or rho)
   int tab_exact;                        // FP64: leading pieces evaluated exactly
   double wscale;                        // -G, times s^3 on the FP32 path
@@ -162,6 +163,18 @@ __device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
   const float x = TAB ? __builtin_fmaf(q, inv, -A.tab_off)
                       : __builtin_amdgcn_sqrtf(r2) * A.tab_s;   // >= 0
   const int k = (int)x;                 // <= kSplitBins since r < r_c
+  const float t = __builtin_amdgcn_fractf(x);
+  const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
+  return f * (inv * inv * inv);
+}
+
+// The same weight from rho^2 = r^2 + eps^2 (floored as above): q = s^2 rho^2.
+__device__ __forceinline__ float pair_weight_rho(float rho2, const PairArgs<float>& A,
+                                                 const SplitTable<float>& tab) {
+  const float q = rho2 * A.tab_s2;
+  const float inv = __builtin_amdgcn_rsqf(q);
+  const float x = __builtin_fmaf(q, inv, -A.tab_off);
+  const int k = (int)x;
   const float t = __builtin_amdgcn_fractf(x);
   const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
   return f * (inv * inv * inv);
@@ -453,19 +466,45 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
         }
         continue;
       }
+      // RHO (FP32 force over the softened-distance table): the squared
+      // separation is accumulated on top of eps^2, so the test compares
+      // rho^2 = r^2 + eps^2 with r_c^2 + eps^2 and the weight starts from rho^2
+      constexpr bool RHO = sizeof(T) == 4 && TAB == 1 && !COUNT;
+      const T cut2 = RHO ? A.rho_cut2 : A.rc2;
+      // FP64 reads the next staged j while the current one is tested
+      // (measured 3 % faster; FP32 gains nothing and spills more)
+      constexpr bool PF = sizeof(T) == 8;
+      T4 pn = jp[0];
 #pragma unroll 2
       for (int t = 0; t < iters; ++t) {
-        const T4& pj = jp[t * ns];
+        T4 pj;
+        if constexpr (PF) {
+          pj = pn;
+          pn = jp[min(t + 1, iters - 1) * ns];
+        } else {
+          pj = jp[t * ns];
+        }
         const T jx = pj.x, jy = pj.y, jz = pj.z;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const T dx = xi[u] - jx, dy = yi[u] - jy, dz = zi[u] - jz;
-          const T r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < A.rc2) {
+          T r2;
+          if constexpr (RHO) {
+            r2 = __builtin_fmaf(dx, dx, A.rho_e2);
+            r2 = __builtin_fmaf(dy, dy, r2);
+            r2 = __builtin_fmaf(dz, dz, r2);
+          } else {
+            r2 = dx * dx + dy * dy + dz * dz;
+          }
+          if (r2 < cut2) {
             if (COUNT) {
               npairs += r2 > T(0) ? 1 : 0;
             } else {
-              T w = pair_weight<TAB>(r2, A, S.tab);
+              T w;
+              if constexpr (RHO)
+                w = pair_weight_rho(r2, A, S.tab);
+              else
+                w = pair_weight<TAB>(r2, A, S.tab);
               if (!UM) w *= pj.w;
               ax[u] += w * dx;
               ay[u] += w * dy;
@@ -623,6 +662,8 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.tab_s2 = (float)(s * s);
     A.tab_e2 = (float)std::max(s * s * P->eps * P->eps, 1e-12);
     A.tab_off = (float)(s * P->tab_v0);
+    A.rho_e2 = (float)(std::max(s * s * P->eps * P->eps, 1e-12) / (s * s));
+    A.rho_cut2 = (float)(P->r_c * P->r_c + (double)A.rho_e2);
     A.wscale *= s * s * s;
     A.vjp_k5 = (T)(3.0 * s * s);
     A.vjp_e2 = (T)(-1.4426950408889634 / (4.0 * P->r_s * P->r_s));
