@@ -103,7 +103,14 @@ int p3m_plan_destroy(p3m_plan* plan);
 /* Change the stream later calls on this plan enqueue on. */
 int p3m_plan_set_stream(p3m_plan* plan, void* hip_stream);
 
-/* Full P3M force (PP + PM) on n particles.
+/* Full P3M force (PP + PM) on n particles. After binning on the plan's
+ * stream, the mesh part (deposit, Poisson solve) runs on a second stream of
+ * the plan (default priority) beside the pair sum, which writes the force;
+ * the plan's stream then waits for it and the interpolation adds the mesh
+ * force. To the caller all of it is ordered on the plan's stream, as one
+ * call. Stage timers of deposit and FFT are recorded on the second stream,
+ * so they include the time those kernels wait for compute units held by
+ * the pair sum.
  *   pos         device, double [3][n], components in [0, box)
  *   mass        device, double [n], or NULL to give every particle mass_scalar
  *               (one mass per particle group, guide Ch. 6)

@@ -48,6 +48,11 @@ void free_workspace(p3m_plan* P) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->stream2) (void)hipStreamDestroy(P->stream2);
+  P->ev_fork = P->ev_join = nullptr;
+  P->stream2 = nullptr;
 }
 
 void free_timers(p3m_plan* P) {
@@ -98,6 +103,14 @@ void begin_call(p3m_plan* P) {
 
 enum class Part { kP3M, kPM, kPP };
 
+// Launches that take the plan's stream enqueue on `s` while this is alive.
+struct OnStream {
+  p3m_plan* P;
+  hipStream_t saved;
+  OnStream(p3m_plan* p, hipStream_t s) : P(p), saved(p->stream) { P->stream = s; }
+  ~OnStream() { P->stream = saved; }
+};
+
 template <typename T>
 hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
                      double ms, void* force, int f32, Part part) {
@@ -106,6 +119,34 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
     StageTimer t(P, P3M_STAGE_BIN);
     if ((e = launch_bin(P, n, pos, mass, ms)) != hipSuccess) return e;
     if (part != Part::kPM && (e = launch_items(P)) != hipSuccess) return e;
+  }
+  if (part == Part::kP3M) {
+    // The mesh part (deposit, Poisson solve) on the second stream beside the
+    // pair sum, which writes the force; the interpolation then adds the mesh
+    // force once both are done. Both read the binned particles only.
+    const hipStream_t main = P->stream;
+    if ((e = hipEventRecord(P->ev_fork, main)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(P->stream2, P->ev_fork, 0)) != hipSuccess) return e;
+    {
+      OnStream on(P, P->stream2);
+      {
+        StageTimer t(P, P3M_STAGE_DEPOSIT);
+        if ((e = launch_deposit<T>(P)) != hipSuccess) return e;
+      }
+      {
+        StageTimer t(P, P3M_STAGE_FFT);
+        if ((e = launch_fft_poisson<T>(P)) != hipSuccess) return e;
+      }
+      if ((e = hipEventRecord(P->ev_join, P->stream2)) != hipSuccess) return e;
+    }
+    {
+      StageTimer t(P, P3M_STAGE_PP);
+      if ((e = launch_pairs<T>(P, n, false, force, f32, mass == nullptr)) != hipSuccess)
+        return e;
+    }
+    if ((e = hipStreamWaitEvent(main, P->ev_join, 0)) != hipSuccess) return e;
+    StageTimer t(P, P3M_STAGE_INTERP);
+    return launch_interp<T>(P, n, force, f32, true);
   }
   if (part != Part::kPP) {
     {
@@ -543,6 +584,10 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
     W.grid2 = dev_alloc<unsigned char>(P->ncell * real, err);
     W.lam_grid = dev_alloc<unsigned char>(3 * P->ncell * real, err);
   }
+  // the P3M force's second stream (default priority) and its fork / join events
+  if (err == hipSuccess) err = hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
   if (err == hipSuccess) {
     int32_t* rows = new (std::nothrow) int32_t[4 * (size_t)P->nrows];
     if (!rows) {

@@ -68,6 +68,10 @@ struct p3m_plan {
   p3m_params prm{};
   int64_t n_max = 0;
   hipStream_t stream = nullptr;
+  // second stream of the P3M force: the mesh part (deposit, Poisson solve)
+  // runs on it while the pair sum runs on `stream`; events fork and join
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
   // geometry
   int ng = 0, lg = 0;           // grid cells per side and its log2
@@ -112,7 +116,8 @@ hipError_t launch_deposit3(p3m_plan* P, const void* lam, void* grids);   // m * 
 template <typename T>
 hipError_t launch_fft_poisson(p3m_plan* P);
 template <typename T>
-hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32);
+hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
+                         bool accumulate = false);
 template <typename T>
 hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out,
                         int force_fp32, bool uniform_mass);
