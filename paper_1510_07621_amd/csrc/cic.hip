@@ -90,7 +90,8 @@ __global__ void __launch_bounds__(kThreads)
 k_interp(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict__ skey,
          const int32_t* __restrict__ start, int ng, int lg, T inv_h, const T* __restrict__ phi,
          T c1, T c2, typename Vec<T>::v4* __restrict__ acc_out, const int32_t* __restrict__ perm,
-         int64_t n, void* __restrict__ force, int force_fp32, int accumulate) {
+         int64_t n, void* __restrict__ force, int force_fp32,
+         const typename Vec<T>::v4* __restrict__ acc_pp) {
   __shared__ T ph[kN5 * kN5 * kN5];
   __shared__ T gr[3][kN1 * kN1 * kN1];
   __shared__ BrickRuns R;
@@ -140,19 +141,23 @@ k_interp(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict_
     } else {
       int64_t i = perm[s];
       double m = (double)p.w;
-      // accumulate: add to the force the pair sum wrote (the P3M call whose
-      // mesh part ran beside the pair sum)
-      const double fx = -m * (double)ax, fy = -m * (double)ay, fz = -m * (double)az;
+      // acc_pp: the pair sum's sorted acceleration, added here (the P3M call
+      // whose mesh part ran beside the pair sum)
+      double gx = -(double)ax, gy = -(double)ay, gz = -(double)az;
+      if (acc_pp) {
+        const typename Vec<T>::v4 a = acc_pp[s];
+        gx += (double)a.x; gy += (double)a.y; gz += (double)a.z;
+      }
       if (force_fp32) {
         float* F = (float*)force;
-        F[i] = (float)(accumulate ? (double)F[i] + fx : fx);
-        F[n + i] = (float)(accumulate ? (double)F[n + i] + fy : fy);
-        F[2 * n + i] = (float)(accumulate ? (double)F[2 * n + i] + fz : fz);
+        F[i] = (float)(m * gx);
+        F[n + i] = (float)(m * gy);
+        F[2 * n + i] = (float)(m * gz);
       } else {
         double* F = (double*)force;
-        F[i] = accumulate ? F[i] + fx : fx;
-        F[n + i] = accumulate ? F[n + i] + fy : fy;
-        F[2 * n + i] = accumulate ? F[2 * n + i] + fz : fz;
+        F[i] = m * gx;
+        F[n + i] = m * gy;
+        F[2 * n + i] = m * gz;
       }
     }
   }
@@ -182,7 +187,7 @@ hipError_t launch_deposit3(p3m_plan* P, const void* lam, void* grids) {
 
 template <typename T>
 hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
-                         bool accumulate) {
+                         const void* acc_pp) {
   Workspace& W = P->ws;
   int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
   double h = P->h;
@@ -198,7 +203,8 @@ hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32
   k_interp<T><<<nb, kThreads, 0, P->stream>>>((const typename Vec<T>::v4*)W.rec, W.skey,
                                               W.start, P->ng, P->lg, T(1.0 / h),
                                               (const T*)W.grid, c1, c2, acc, W.perm, n,
-                                              force_out, force_fp32, accumulate ? 1 : 0);
+                                              force_out, force_fp32,
+                                              (const typename Vec<T>::v4*)acc_pp);
   return hipGetLastError();
 }
 
@@ -206,7 +212,7 @@ template hipError_t launch_deposit<float>(p3m_plan*);
 template hipError_t launch_deposit<double>(p3m_plan*);
 template hipError_t launch_deposit3<float>(p3m_plan*, const void*, void*);
 template hipError_t launch_deposit3<double>(p3m_plan*, const void*, void*);
-template hipError_t launch_interp<float>(p3m_plan*, int64_t, void*, int, bool);
-template hipError_t launch_interp<double>(p3m_plan*, int64_t, void*, int, bool);
+template hipError_t launch_interp<float>(p3m_plan*, int64_t, void*, int, const void*);
+template hipError_t launch_interp<double>(p3m_plan*, int64_t, void*, int, const void*);
 
 }  // namespace p3m

@@ -122,8 +122,9 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
   }
   if (part == Part::kP3M) {
     // The mesh part (deposit, Poisson solve) on the second stream beside the
-    // pair sum, which writes the force; the interpolation then adds the mesh
-    // force once both are done. Both read the binned particles only.
+    // pair sum, which writes its sorted acceleration; the interpolation then
+    // adds the mesh acceleration and writes the force once both are done.
+    // Both read the binned particles only.
     const hipStream_t main = P->stream;
     if ((e = hipEventRecord(P->ev_fork, main)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(P->stream2, P->ev_fork, 0)) != hipSuccess) return e;
@@ -141,12 +142,13 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
     }
     {
       StageTimer t(P, P3M_STAGE_PP);
-      if ((e = launch_pairs<T>(P, n, false, force, f32, mass == nullptr)) != hipSuccess)
+      if ((e = launch_pairs<T>(P, n, false, nullptr, f32, mass == nullptr, P->ws.acc_pm)) !=
+          hipSuccess)
         return e;
     }
     if ((e = hipStreamWaitEvent(main, P->ev_join, 0)) != hipSuccess) return e;
     StageTimer t(P, P3M_STAGE_INTERP);
-    return launch_interp<T>(P, n, force, f32, true);
+    return launch_interp<T>(P, n, force, f32, P->ws.acc_pm);
   }
   if (part != Part::kPP) {
     {

@@ -117,10 +117,10 @@ template <typename T>
 hipError_t launch_fft_poisson(p3m_plan* P);
 template <typename T>
 hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
-                         bool accumulate = false);
+                         const void* acc_pp = nullptr);
 template <typename T>
-hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out,
-                        int force_fp32, bool uniform_mass);
+hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32,
+                        bool uniform_mass, void* acc_out = nullptr);
 template <typename T>
 hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
 template <typename T>

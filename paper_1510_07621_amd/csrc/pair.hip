@@ -90,6 +90,7 @@ struct PairArgs {
   const typename Vec<T>::v4* __restrict__ lam;
   T vjp_ce, vjp_k5, vjp_e2;
   const typename Vec<T>::v4* __restrict__ acc_pm;  // sorted PM acceleration or null
+  typename Vec<T>::v4* __restrict__ acc_out;       // sorted output acceleration or null
   const int32_t* __restrict__ perm;
   int64_t n;
   void* __restrict__ force;
@@ -557,6 +558,12 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
       const T4 pm = A.acc_pm[s];
       gx += (double)pm.x; gy += (double)pm.y; gz += (double)pm.z;
     }
+    if (A.acc_out) {            // sorted acceleration, for the mesh part to add to
+      T4 o;
+      o.x = (T)gx; o.y = (T)gy; o.z = (T)gz; o.w = T(0);
+      A.acc_out[s] = o;
+      continue;
+    }
     const int64_t i = A.perm[s];
     if (A.force_fp32) {
       float* F = (float*)A.force;
@@ -680,9 +687,10 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
 
 template <typename T>
 hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32,
-                        bool uniform_mass) {
+                        bool uniform_mass, void* acc_out) {
   PairArgs<T> A = make_args<T>(P, n);
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
+  A.acc_out = (typename Vec<T>::v4*)acc_out;
   A.force = force_out;
   A.force_fp32 = force_fp32;
   const unsigned grid = pair_grid(P);
@@ -733,8 +741,8 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
   return hipGetLastError();
 }
 
-template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int, bool);
-template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, bool);
+template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int, bool, void*);
+template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, bool, void*);
 template hipError_t launch_pairs_vjp<float>(p3m_plan*, int64_t, bool, double*, bool);
 template hipError_t launch_pairs_vjp<double>(p3m_plan*, int64_t, bool, double*, bool);
 template hipError_t launch_pair_count<float>(p3m_plan*, int64_t, int64_t*);
