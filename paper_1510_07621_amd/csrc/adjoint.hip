@@ -70,7 +70,8 @@ k_interp_vjp(const typename Vec<T>::v4* __restrict__ rec,
              const int32_t* __restrict__ start, int ng, int lg, T inv_h, T inv_h3,
              const T* __restrict__ phi, const T* __restrict__ psi, T c1, T c2,
              typename Vec<T>::v4* __restrict__ acc_out, const int32_t* __restrict__ perm,
-             int64_t n, double* __restrict__ pos_bar) {
+             int64_t n, double* __restrict__ pos_bar,
+             const typename Vec<T>::v4* __restrict__ acc_pp) {
   __shared__ T ph[kN5 * kN5 * kN5];
   __shared__ T gr[3][kN1 * kN1 * kN1];
   __shared__ T ps[kN1 * kN1 * kN1];
@@ -126,11 +127,18 @@ k_interp_vjp(const typename Vec<T>::v4* __restrict__ rec,
       o.x = bx; o.y = by; o.z = bz; o.w = T(0);
       acc_out[s] = o;
     } else {
+      // acc_pp: the pair adjoint's sorted cotangent, added here (the P3M
+      // call whose mesh part ran beside the pair adjoint)
+      double gx = (double)bx, gy = (double)by, gz = (double)bz;
+      if (acc_pp) {
+        const typename Vec<T>::v4 a = acc_pp[s];
+        gx += (double)a.x; gy += (double)a.y; gz += (double)a.z;
+      }
       const int64_t i = perm[s];
       const double m = (double)p.w;
-      pos_bar[i] = m * (double)bx;
-      pos_bar[n + i] = m * (double)by;
-      pos_bar[2 * n + i] = m * (double)bz;
+      pos_bar[i] = m * gx;
+      pos_bar[n + i] = m * gy;
+      pos_bar[2 * n + i] = m * gz;
     }
   }
 }
@@ -185,7 +193,7 @@ hipError_t launch_deposit_lambda(p3m_plan* P) {
 }
 
 template <typename T>
-hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar) {
+hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar, const void* acc_pp) {
   Workspace& W = P->ws;
   const int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
   T c1, c2;
@@ -195,7 +203,7 @@ hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar) {
   k_interp_vjp<T><<<nb, kThreads, 0, P->stream>>>(
       (const typename Vec<T>::v4*)W.rec, (const typename Vec<T>::v4*)W.lam, W.skey, W.start,
       P->ng, P->lg, T(1.0 / h), T(1.0 / (h * h * h)), (const T*)W.grid, (const T*)W.grid2, c1,
-      c2, acc, W.perm, n, pos_bar);
+      c2, acc, W.perm, n, pos_bar, (const typename Vec<T>::v4*)acc_pp);
   return hipGetLastError();
 }
 
@@ -209,7 +217,7 @@ template hipError_t launch_lambda_sort<float>(p3m_plan*, int64_t, const double*)
 template hipError_t launch_lambda_sort<double>(p3m_plan*, int64_t, const double*);
 template hipError_t launch_deposit_lambda<float>(p3m_plan*);
 template hipError_t launch_deposit_lambda<double>(p3m_plan*);
-template hipError_t launch_interp_vjp<float>(p3m_plan*, int64_t, double*);
-template hipError_t launch_interp_vjp<double>(p3m_plan*, int64_t, double*);
+template hipError_t launch_interp_vjp<float>(p3m_plan*, int64_t, double*, const void*);
+template hipError_t launch_interp_vjp<double>(p3m_plan*, int64_t, double*, const void*);
 
 }  // namespace p3m

@@ -205,6 +205,40 @@ hipError_t run_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass
     if (part != Part::kPM && (e = launch_items(P)) != hipSuccess) return e;
     if ((e = launch_lambda_sort<T>(P, n, fbar)) != hipSuccess) return e;
   }
+  if (part == Part::kP3M) {
+    // As in the force: the mesh adjoint's deposits and Poisson solves on the
+    // second stream beside the pair adjoint, which writes its sorted
+    // cotangent; the gather then adds the mesh part and writes pos_bar.
+    const hipStream_t main = P->stream;
+    if ((e = hipEventRecord(P->ev_fork, main)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(P->stream2, P->ev_fork, 0)) != hipSuccess) return e;
+    {
+      OnStream on(P, P->stream2);
+      {
+        StageTimer t(P, P3M_STAGE_DEPOSIT);
+        if ((e = launch_deposit<T>(P)) != hipSuccess) return e;
+        if ((e = launch_deposit_lambda<T>(P)) != hipSuccess) return e;
+      }
+      {
+        StageTimer t(P, P3M_STAGE_FFT);
+        if ((e = launch_fft_poisson<T>(P)) != hipSuccess) return e;
+        std::swap(W.grid, W.grid2);
+        e = launch_fft_poisson<T>(P);
+        std::swap(W.grid, W.grid2);
+        if (e != hipSuccess) return e;
+      }
+      if ((e = hipEventRecord(P->ev_join, P->stream2)) != hipSuccess) return e;
+    }
+    {
+      StageTimer t(P, P3M_STAGE_PP);
+      if ((e = launch_pairs_vjp<T>(P, n, false, pbar, mass == nullptr, W.acc_pm)) !=
+          hipSuccess)
+        return e;
+    }
+    if ((e = hipStreamWaitEvent(main, P->ev_join, 0)) != hipSuccess) return e;
+    StageTimer t(P, P3M_STAGE_INTERP);
+    return launch_interp_vjp<T>(P, n, pbar, W.acc_pm);
+  }
   if (part != Part::kPP) {
     {
       StageTimer t(P, P3M_STAGE_DEPOSIT);

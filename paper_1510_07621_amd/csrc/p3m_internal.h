@@ -140,10 +140,11 @@ hipError_t launch_lambda_sort(p3m_plan* P, int64_t n, const double* force_bar);
 template <typename T>
 hipError_t launch_deposit_lambda(p3m_plan* P);   // divergence of the deposit -> grid2
 template <typename T>
-hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar);
+hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar,
+                             const void* acc_pp = nullptr);
 template <typename T>
 hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar,
-                            bool uniform_mass);
+                            bool uniform_mass, void* acc_out = nullptr);
 hipError_t launch_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar,
                             const double* mass, double ms, double c, hipStream_t s);
 hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,

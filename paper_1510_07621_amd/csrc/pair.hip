@@ -710,9 +710,10 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
 
 template <typename T>
 hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar,
-                            bool uniform_mass) {
+                            bool uniform_mass, void* acc_out) {
   PairArgs<T> A = make_args<T>(P, n);
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
+  A.acc_out = (typename Vec<T>::v4*)acc_out;
   A.lam = (const typename Vec<T>::v4*)P->ws.lam;
   A.force = pos_bar;
   A.force_fp32 = 0;
@@ -743,8 +744,8 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out) {
 
 template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int, bool, void*);
 template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, bool, void*);
-template hipError_t launch_pairs_vjp<float>(p3m_plan*, int64_t, bool, double*, bool);
-template hipError_t launch_pairs_vjp<double>(p3m_plan*, int64_t, bool, double*, bool);
+template hipError_t launch_pairs_vjp<float>(p3m_plan*, int64_t, bool, double*, bool, void*);
+template hipError_t launch_pairs_vjp<double>(p3m_plan*, int64_t, bool, double*, bool, void*);
 template hipError_t launch_pair_count<float>(p3m_plan*, int64_t, int64_t*);
 template hipError_t launch_pair_count<double>(p3m_plan*, int64_t, int64_t*);
 
