@@ -82,6 +82,7 @@ struct PairArgs {
   const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
   float rho_e2, rho_cut2;               // tab_e2 / tab_s2 and r_c^2 + rho_e2
+  double rho_cut2d;                     // FP64: r_c^2 + eps^2
   double tab_s64, tab_off64;            // FP64 table: x = s v - s v0 (v = r or rho)
   int tab_exact;                        // FP64: leading pieces evaluated exactly
   double wscale;                        // -G, times s^3 on the FP32 path
@@ -128,6 +129,17 @@ __device__ __forceinline__ double split_f64_series(double r2, double inv2rs) {
 #pragma unroll
   for (int n = kSeriesTerms - 2; n >= 0; --n) p = fma(p, s, series_coef(n));
   return 1.0 - 2.2567583341910251 * (sqrt(r2) * inv2rs) * s * p;
+}
+
+// 1 / sqrt(q) to FP64 rounding for q > 0: the hardware estimate refined by
+// one third-order step, y (1 + e/2 + 3e^2/8) with e = 1 - q y^2 (cubic
+// convergence from its roughly 23 correct bits). No fix-ups for zero,
+// infinite or negative q: the only such case, q = 0 (a self pair without
+// softening), has its weight discarded by the caller.
+__device__ __forceinline__ double rsqrt_pos(double q) {
+  const double y = __builtin_amdgcn_rsq(q);
+  const double e = fma(-q * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 // FP64 split factor f from the table. TAB 1: the variable is the softened
@@ -185,9 +197,29 @@ template <int TAB>
 __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>& A,
                                               const SplitTable<double>& tab) {
   const double q = r2 + A.eps2;
-  const double inv = rsqrt(q);
+  const double inv = rsqrt_pos(q);
   const double f = split_f64<TAB>(r2, q, inv, A, tab);
   return r2 > 0.0 ? f * (inv * inv * inv) : 0.0;   // eps may be 0
+}
+
+// The same weight (softened-distance table) from rho^2 = r^2 + eps^2; r^2
+// itself is formed only for the series pieces. A pair whose rho^2 rounds to
+// eps^2 (the self pair) gets weight 0.
+__device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<double>& A,
+                                                  const SplitTable<double>& tab) {
+  const double inv = rsqrt_pos(q);
+  const double x = fma(q * inv, A.tab_s64, -A.tab_off64);
+  const int k = min(max((int)x, 0), kSplitBins);
+  double f;
+  if (k < A.tab_exact) {
+    f = split_f64_series(fmax(q - A.eps2, 0.0), A.inv2rs);
+  } else {
+    const double tau = 2.0 * (x - (double)k) - 1.0;
+    f = tab.c[kSplitCoef64 - 1][k];
+#pragma unroll
+    for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * tau + tab.c[l][k];
+  }
+  return q > A.eps2 ? f * (inv * inv * inv) : 0.0;
 }
 
 // Adjoint weights of a pair: with g = f / rho^3 and the pair Jacobian
@@ -218,7 +250,7 @@ __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<doubl
                                                  const SplitTable<double>& tab, double& w1,
                                                  double& w2) {
   const double q = r2 + A.eps2;
-  const double inv = rsqrt(q);
+  const double inv = rsqrt_pos(q);
   const double r = sqrt(r2);
   const double u = r * A.inv2rs;
   const double e = exp(-u * u);
@@ -467,11 +499,12 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
         }
         continue;
       }
-      // RHO (FP32 force over the softened-distance table): the squared
-      // separation is accumulated on top of eps^2, so the test compares
+      // RHO (force over the softened-distance table): the squared separation
+      // is accumulated on top of eps^2, so the test compares
       // rho^2 = r^2 + eps^2 with r_c^2 + eps^2 and the weight starts from rho^2
-      constexpr bool RHO = sizeof(T) == 4 && TAB == 1 && !COUNT;
-      const T cut2 = RHO ? A.rho_cut2 : A.rc2;
+      constexpr bool RHO = TAB == 1 && !COUNT;
+      const T e2r = sizeof(T) == 4 ? T(A.rho_e2) : A.eps2;
+      const T cut2 = RHO ? (sizeof(T) == 4 ? T(A.rho_cut2) : T(A.rho_cut2d)) : A.rc2;
       // FP64 reads the next staged j while the current one is tested
       // (measured 3 % faster; FP32 gains nothing and spills more)
       constexpr bool PF = sizeof(T) == 8;
@@ -491,9 +524,9 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
           const T dx = xi[u] - jx, dy = yi[u] - jy, dz = zi[u] - jz;
           T r2;
           if constexpr (RHO) {
-            r2 = __builtin_fmaf(dx, dx, A.rho_e2);
-            r2 = __builtin_fmaf(dy, dy, r2);
-            r2 = __builtin_fmaf(dz, dz, r2);
+            r2 = fma(dx, dx, e2r);
+            r2 = fma(dy, dy, r2);
+            r2 = fma(dz, dz, r2);
           } else {
             r2 = dx * dx + dy * dy + dz * dz;
           }
@@ -653,6 +686,7 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.h = (T)P->h;
   A.rc2 = (T)(P->r_c * P->r_c);
   A.eps2 = (T)(P->eps * P->eps);
+  A.rho_cut2d = P->r_c * P->r_c + P->eps * P->eps;
   A.inv2rs = (T)(1.0 / (2.0 * P->r_s));
   A.wscale = -P->prm.G;
   if constexpr (sizeof(T) == 8) {
