@@ -52,8 +52,8 @@ int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32
  * leading bins (next to the kink at r = 0, with r / (2 r_s) <= 0.9) miss
  * twice the accuracy of the table over r (at least 4e-16); the pair sum
  * evaluates those bins with a power series of f. [v0, v1] is cut into B equal
- * bins; with x = (v - v0) B / (v1 - v0), k = floor(x), tau = 2 (x - k) - 1,
- * f = sum_{l=0..6} c_l[k] tau^l, the degree-6 polynomial through f at the
+ * bins; with x = (v - v0) B / (v1 - v0), k = floor(x), t = x - k,
+ * f = sum_{l=0..6} c_l[k] t^l, the degree-6 polynomial through f at the
  * seven Chebyshev points of bin k (fitted in extended precision); entry B is
  * the constant f at v1. Layout: out[l * (B + 1) + k], l = 0..6, k = 0..B;
  * map_out (may be NULL) receives {variable (0: r, 1: softened distance), v0,

@@ -166,8 +166,9 @@ def split_table(cutoff_rs: float, softening_rs: float = 0.0):
 
 def split_table64(cutoff_rs: float, softening_rs: float = 0.0):
     """FP64 split-factor table of the pair sum: a (7, B + 1) float64 array, row
-    l the coefficient of tau^l of each bin, and the map (variable, v0, v1,
-    exact bins) as for split_table plus the leading bins evaluated exactly."""
+    l the coefficient of t^l (t the position in the bin, 0..1) of each bin,
+    and the map (variable, v0, v1, exact bins) as for split_table plus the
+    leading bins evaluated exactly."""
     import numpy as np
     b = _lib.p3m_split_table64(cutoff_rs, softening_rs, None, 0, None)
     _check(min(b, 0), "p3m_split_table64")

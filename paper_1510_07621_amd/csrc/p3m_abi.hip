@@ -363,8 +363,8 @@ SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out) {
 }
 
 // One set of degree-6 pieces of g over [v0, v1] in extended precision:
-// piece k covers v = v0 + (k + t)(v1 - v0)/B, t in [0, 1]; with tau = 2t - 1
-// the polynomial through g at the seven Chebyshev points of [-1, 1] (the
+// piece k covers v = v0 + (k + t)(v1 - v0)/B, t in [0, 1]; in powers of t,
+// the polynomial through g at the seven Chebyshev points of [0, 1] (the
 // pieces are narrow, so the coefficients fall off fast and only the final
 // rounding to double remains). err[k]: the largest deviation from g of the
 // rounded piece on a dense sample.
@@ -384,10 +384,10 @@ static void fit_table64(int var, long double e, long double v0, long double v1, 
   for (int k = 0; k < B; ++k) {
     LD V[kSplitCoef64][kSplitCoef64 + 1];
     for (int j = 0; j < C; ++j) {
-      LD tau = std::cos((2 * j + 1) * kPi / (2 * C));
+      LD t = 0.5L - 0.5L * std::cos((2 * j + 1) * kPi / (2 * C));
       LD p = 1.0L;
-      for (int l = 0; l < C; ++l, p *= tau) V[j][l] = p;
-      V[j][C] = g(v0 + w * ((LD)k + 0.5L * (tau + 1.0L)));
+      for (int l = 0; l < C; ++l, p *= t) V[j][l] = p;
+      V[j][C] = g(v0 + w * ((LD)k + t));
     }
     for (int col = 0; col < C; ++col) {     // Gauss-Jordan, partial pivoting
       int piv = col;
@@ -403,9 +403,9 @@ static void fit_table64(int var, long double e, long double v0, long double v1, 
     for (int l = 0; l < C; ++l) out[l * stride + k] = (double)(V[l][C] / V[l][l]);
     err[k] = 0;
     for (int j = 0; j <= 32; ++j) {
-      LD tau = -1.0L + j / 16.0L, p = 0;
-      for (int l = C - 1; l >= 0; --l) p = p * tau + (LD)out[l * stride + k];
-      err[k] = std::max(err[k], std::fabs(p - g(v0 + w * ((LD)k + 0.5L * (tau + 1.0L)))));
+      LD t = j / 32.0L, p = 0;
+      for (int l = C - 1; l >= 0; --l) p = p * t + (LD)out[l * stride + k];
+      err[k] = std::max(err[k], std::fabs(p - g(v0 + w * ((LD)k + t))));
     }
   }
   out[B] = (double)g(v1);

@@ -163,8 +163,8 @@ struct SplitMap {
   int exact;    // FP64: leading pieces the kernel replaces by the exact formula
 };
 SplitMap split_table(double cutoff_rs, double soft_rs, int bins, float* out);
-// FP64 table: out[l * (kSplitBins + 1) + k] is the coefficient of tau^l
-// (tau = 2t - 1) of piece k of the same variable choice; entry kSplitBins is
+// FP64 table: out[l * (kSplitBins + 1) + k] is the coefficient of t^l
+// (t in [0, 1) across the bin) of piece k of the same variable choice; entry kSplitBins is
 // the constant value at v1.
 SplitMap split_table64(double cutoff_rs, double soft_rs, double* out);
 

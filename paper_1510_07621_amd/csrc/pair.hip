@@ -101,7 +101,7 @@ struct PairArgs {
 
 // The split-factor table in LDS, one array per coefficient so that the
 // random per-lane bin lookups spread over the banks. FP32: cubic pieces in
-// t in [0, 1); FP64: degree-6 pieces in tau = 2t - 1 in [-1, 1).
+// t in [0, 1); FP64: degree-6 pieces in t as well.
 constexpr int kTabStride = kSplitBins + 1;
 template <typename T> struct SplitTable;
 template <> struct SplitTable<float> {
@@ -155,10 +155,10 @@ __device__ __forceinline__ double split_f64(double r2, double q, double inv,
   const double x = TAB ? fma(q * inv, A.tab_s64, -A.tab_off64) : sqrt(r2) * A.tab_s64;
   const int k = min(max((int)x, 0), kSplitBins);   // x >= 0 and k <= kSplitBins for r < r_c
   if (TAB && k < A.tab_exact) return split_f64_series(r2, A.inv2rs);
-  const double tau = 2.0 * (x - (double)k) - 1.0;
+  const double t = __builtin_amdgcn_fract(x);     // x >= 0 (k = 64: constant piece)
   double f = tab.c[kSplitCoef64 - 1][k];
 #pragma unroll
-  for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * tau + tab.c[l][k];
+  for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * t + tab.c[l][k];
   return f;
 }
 
@@ -214,10 +214,10 @@ __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<doubl
   if (k < A.tab_exact) {
     f = split_f64_series(fmax(q - A.eps2, 0.0), A.inv2rs);
   } else {
-    const double tau = 2.0 * (x - (double)k) - 1.0;
+    const double t = __builtin_amdgcn_fract(x);
     f = tab.c[kSplitCoef64 - 1][k];
 #pragma unroll
-    for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * tau + tab.c[l][k];
+    for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * t + tab.c[l][k];
   }
   return q > A.eps2 ? f * (inv * inv * inv) : 0.0;
 }

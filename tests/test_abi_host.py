@@ -235,10 +235,10 @@ def test_split_table64_matches_erfc_split(b, cutoff_rs, soft_rs, var):
     x = (vv - v0) * (B / (v1 - v0))
     assert x.min() >= 0
     k = np.minimum(x.astype(np.int64), B)
-    tau = 2.0 * (x - k) - 1.0
+    t = x - k
     f = tab[6][k]
     for l in range(5, -1, -1):
-        f = f * tau + tab[l][k]
+        f = f * t + tab[l][k]
     f = np.where(k < exact, _split_f(0.5 * r), f)
     assert np.max(np.abs(f - _split_f(0.5 * r))) < (3e-15 if cutoff_rs <= 4.5 else 3e-14)
     if soft_rs == 0.0:
