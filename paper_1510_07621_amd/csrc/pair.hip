@@ -89,7 +89,7 @@ struct PairArgs {
   // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
   // pair Hessian (see pair_vjp_weights)
   const typename Vec<T>::v4* __restrict__ lam;
-  T vjp_ce, vjp_k5, vjp_e2;
+  T vjp_ce, vjp_k5, vjp_e2, vjp_s;
   const typename Vec<T>::v4* __restrict__ acc_pm;  // sorted PM acceleration or null
   typename Vec<T>::v4* __restrict__ acc_out;       // sorted output acceleration or null
   const int32_t* __restrict__ perm;
@@ -224,9 +224,16 @@ __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<doubl
 
 // Adjoint weights of a pair: with g = f / rho^3 and the pair Jacobian
 // J = g I + (g'(r)/r) r r^T, J dl = w1 dl + w2 (r . dl) r, where
-// w1 = g and w2 = g'(r)/r = -(r e^{-u^2} / (2 sqrt(pi) r_s^3)) / rho^3 - 3 f / rho^5,
-// both (FP32) in the scaled units of pair_weight: rsq(q) = 1 / (s rho), the
-// common factor s^3 folded into wscale, vjp_k5 = 3 s^2; FP64: s = 1.
+// w1 = g and w2 = g'(r)/r = d / rho^3 - 3 f / rho^5, d = f'(r) / r.
+// Over the softened-distance table (TAB 1), d = (df/drho) / rho, and df/drho
+// is s times the derivative of the piece in its position t (the piece's
+// derivative misses f' by at most a few 1e-6 of w2 in FP32, 4e-11 in FP64,
+// both at the cutoff); the FP64 leading pieces evaluated exactly take
+// d = -r e^{-u^2} / (2 sqrt(pi) r_s^3) with e^{-u^2} from its series. Over r
+// (TAB 0, wide softening) d comes from that formula with the library
+// exponential. FP32 in the scaled units of pair_weight: rsq(q) = 1 / (s rho),
+// the common factor s^3 folded into wscale, vjp_k5 = 3 s^2, vjp_s = s^2;
+// FP64: physical units, vjp_k5 = 3, vjp_s = s.
 template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>& A,
                                                  const SplitTable<float>& tab, float& w1,
@@ -237,12 +244,28 @@ __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>
                       : __builtin_amdgcn_sqrtf(r2) * A.tab_s;
   const int k = (int)x;
   const float t = __builtin_amdgcn_fractf(x);
-  const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
-  const float inv3 = inv * inv * inv;
-  const float re = __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_exp2f(r2 * A.vjp_e2);
+  const float c1 = tab.c[1][k], c2 = tab.c[2][k], c3 = tab.c[3][k];
+  const float f = tab.c[0][k] + t * (c1 + t * (c2 + t * c3));
+  const float inv2 = inv * inv, inv3 = inv2 * inv;
+  float d;
+  if constexpr (TAB == 1) {
+    const float ft = __builtin_fmaf(t, __builtin_fmaf(3.f * t, c3, c2 + c2), c1);
+    d = A.vjp_s * ft * inv;
+  } else {
+    d = -A.vjp_ce * __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_exp2f(r2 * A.vjp_e2);
+  }
   const bool pos = r2 > 0.f;            // self pairs: zero, never inf * 0
   w1 = pos ? f * inv3 : 0.f;
-  w2 = pos ? -inv3 * (A.vjp_ce * re + A.vjp_k5 * f * (inv * inv)) : 0.f;
+  w2 = pos ? inv3 * (d - A.vjp_k5 * f * inv2) : 0.f;
+}
+
+// e^{-s}, 0 <= s <= 0.81 (u <= 0.9), from its series: 19 terms leave less
+// than 1e-17.
+__device__ __forceinline__ double exp_neg_series(double s) {
+  double p = 1.0;
+#pragma unroll
+  for (int n = 18; n >= 1; --n) p = fma(p, -s * (1.0 / n), 1.0);
+  return p;
 }
 
 template <int TAB>
@@ -251,14 +274,35 @@ __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<doubl
                                                  double& w2) {
   const double q = r2 + A.eps2;
   const double inv = rsqrt_pos(q);
-  const double r = sqrt(r2);
-  const double u = r * A.inv2rs;
-  const double e = exp(-u * u);
-  const double f = split_f64<TAB>(r2, q, inv, A, tab);
-  const double inv3 = inv * inv * inv;
+  const double inv2 = inv * inv, inv3 = inv2 * inv;
+  double f, d;
+  if constexpr (TAB == 1) {
+    const double x = fma(q * inv, A.tab_s64, -A.tab_off64);
+    const int k = min(max((int)x, 0), kSplitBins);
+    if (k < A.tab_exact) {              // next to the kink at r = 0: rare
+      const double u2 = r2 * A.inv2rs * A.inv2rs;
+      f = split_f64_series(r2, A.inv2rs);
+      d = -A.vjp_ce * (r2 * rsqrt_pos(r2)) * exp_neg_series(u2);
+    } else {
+      const double t = __builtin_amdgcn_fract(x);
+      double ft = 0.0;
+      f = tab.c[kSplitCoef64 - 1][k];
+#pragma unroll
+      for (int l = kSplitCoef64 - 2; l >= 0; --l) {
+        ft = fma(ft, t, f);
+        f = fma(f, t, tab.c[l][k]);
+      }
+      d = A.vjp_s * ft * inv;
+    }
+  } else {
+    const double r = sqrt(r2);
+    const double u = r * A.inv2rs;
+    f = split_f64<TAB>(r2, q, inv, A, tab);
+    d = -A.vjp_ce * r * exp(-u * u);
+  }
   const bool pos = r2 > 0.0;                      // eps may be 0
   w1 = pos ? f * inv3 : 0.0;
-  w2 = pos ? -inv3 * (A.vjp_ce * r * e + A.vjp_k5 * f * (inv * inv)) : 0.0;
+  w2 = pos ? inv3 * (d - A.vjp_k5 * f * inv2) : 0.0;
 }
 
 __device__ __forceinline__ int wave_inclusive(int v) {
@@ -707,9 +751,11 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.rho_cut2 = (float)(P->r_c * P->r_c + (double)A.rho_e2);
     A.wscale *= s * s * s;
     A.vjp_k5 = (T)(3.0 * s * s);
+    A.vjp_s = (T)(s * s);
     A.vjp_e2 = (T)(-1.4426950408889634 / (4.0 * P->r_s * P->r_s));
   } else {
     A.vjp_k5 = T(3);
+    A.vjp_s = (T)(kSplitBins / (P->tab64_v1 - P->tab64_v0));
   }
   A.vjp_ce = (T)(1.0 / (2.0 * 1.7724538509055160 * P->r_s * P->r_s * P->r_s));
   A.perm = W.perm;

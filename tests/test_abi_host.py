@@ -179,6 +179,49 @@ def _split_f(u):
     return erfc(u) + 2.0 / np.sqrt(np.pi) * u * np.exp(-u * u)
 
 
+@pytest.mark.parametrize("cutoff_rs,soft_rs", [(4.5, 0.0), (4.5, 0.024), (3.0, 0.024),
+                                               (6.0, 0.01), (4.5, 0.08)])
+def test_adjoint_weight_from_piece_derivatives(b, cutoff_rs, soft_rs):
+    """The force adjoint's second pair weight w2 = g'(r)/r, g = f / rho^3,
+    takes f'(r)/r = (df/drho)/rho from the derivative of the split-factor
+    piece when the table variable is the softened distance. Against the
+    closed form f'(r) = -r^2 e^{-u^2} / (2 sqrt(pi) r_s^3): FP32 pieces within
+    1e-5 of w2 for cutoffs up to 4.5 r_s (2e-4 at 6), FP64 pieces within
+    1e-11 (1e-10 at 6); the FP64 leading exact pieces are excluded (the
+    kernel evaluates those from the closed form)."""
+    import numpy as np
+    r = np.linspace(1e-4, cutoff_rs, 200001)[:-1]           # units of r_s
+    u = 0.5 * r
+    exact_d = -r * np.exp(-u * u) / (2.0 * np.sqrt(np.pi))
+    for prec in ("fp32", "fp64"):
+        if prec == "fp32":
+            tab, (v, v0, v1) = b.split_table(cutoff_rs, soft_rs)
+            exact_bins = 0
+        else:
+            tab, (v, v0, v1, exact_bins) = b.split_table64(cutoff_rs, soft_rs)
+        if v != 1:
+            continue
+        B = tab.shape[1] - 1
+        s = B / (v1 - v0)
+        rho = np.sqrt(r * r + soft_rs * soft_rs)
+        x = (rho - v0) * s
+        k = np.minimum(x.astype(np.int64), B)
+        t = x - k
+        f = tab[-1][k].astype(np.float64)
+        ft = np.zeros_like(t)
+        for l in range(tab.shape[0] - 2, -1, -1):
+            ft = ft * t + f
+            f = f * t + tab[l][k]
+        w2 = s * ft / rho / rho ** 3 - 3.0 * f / rho ** 5
+        w2x = exact_d / rho ** 3 - 3.0 * _split_f(u) / rho ** 5
+        keep = k >= exact_bins
+        rel = np.abs(w2 / w2x - 1.0)[keep]
+        if prec == "fp32":
+            assert rel.max() < (1e-5 if cutoff_rs <= 4.5 else 2e-4)
+        else:
+            assert rel.max() < (1e-11 if cutoff_rs <= 4.5 else 1e-10)
+
+
 @pytest.mark.parametrize("cutoff_rs,soft_rs,var", [
     (4.5, 0.0, 1),          # no softening: the softened distance is r itself
     (4.5, 0.024, 1),        # 0.03 mean spacing at r_s = 1.25 cells
