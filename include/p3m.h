@@ -145,7 +145,14 @@ int pp_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
  *   pos_bar     device output, double [3][n], overwritten; must not overlap
  *               pos, mass or force_bar
  * The plan must have been created with params.adjoint = 1 (else EINVAL).
- * The arithmetic is the plan's precision. n == 0 is a successful no-op. */
+ * The arithmetic is the plan's precision. In J, g'(r) comes from the
+ * derivative of the split-factor pieces the forward pair sum evaluates (the
+ * exact derivative of that piecewise f; within 1e-5 (FP32) / 1e-11 (FP64)
+ * of the closed form for r_c <= 4.5 r_s), except for tables over r (wide
+ * softening) and the FP64 pieces next to r = 0, which use the closed form.
+ * As in p3m_force, the mesh part runs on the plan's second stream beside
+ * the pair part, joined before the call's last kernel on the plan's
+ * stream. n == 0 is a successful no-op. */
 int p3m_force_vjp(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
                   double mass_scalar, const double* force_bar, double* pos_bar);
 
