@@ -95,8 +95,7 @@ def measured_valu():
 def run_steps(binding, plan, x, p, F, m, dt, box, steps):
     """KDK steps; F holds the force at x on entry and on exit."""
     for _ in range(steps):
-        binding.kick(p, F, 0.5 * dt)
-        binding.drift(x, p, m, dt, box)
+        binding.kick_drift(x, p, F, m, 0.5 * dt, dt, box)    # kick, then drift, one pass
         plan.force(x, m, out=F)
         binding.kick(p, F, 0.5 * dt)
 

@@ -229,6 +229,15 @@ int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32,
 int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
               double mass_scalar, double c_drift, double box, void* hip_stream);
 
+/* Kick then drift in one pass (the first half of a kick-drift-kick step):
+ * p <- p + c_kick * F, then x <- wrap(x + c_drift * (p / m)) with the new p;
+ * the same operations in the same order as p3m_kick followed by p3m_drift,
+ * so the results are bitwise the same, with the momenta read and written
+ * once. Arguments as for those two calls; pos and mom must not overlap. */
+int p3m_kick_drift(int64_t n, double* pos, double* mom, const void* force, int32_t force_fp32,
+                   const double* mass, double mass_scalar, double c_kick, double c_drift,
+                   double box, void* hip_stream);
+
 /* Transpose of the drift: x1 = wrap(x + c_drift p / m) has slope 1 in x and
  * c_drift / m in p, so mom_bar <- mom_bar + (c_drift / m) * pos_bar (the
  * quotient first, then one product and one sum per component, no fused

@@ -70,6 +70,7 @@ def _load():
         "pp_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
         "p3m_drift_vjp": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, vp]),
         "p3m_kick": (ctypes.c_int, [i64, vp, vp, i32, dbl, vp]),
+        "p3m_kick_drift": (ctypes.c_int, [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, vp]),
         "p3m_drift": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, dbl, vp]),
         "p3m_set_timing": (ctypes.c_int, [vp, i32]),
         "p3m_stage_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), i32]),
@@ -391,6 +392,24 @@ def kick(mom: torch.Tensor, force: torch.Tensor, c_kick: float) -> torch.Tensor:
     _check(_lib.p3m_kick(n, _ptr(mom), _ptr(force), 1 if force.dtype == torch.float32 else 0,
                          float(c_kick), _stream_ptr()), "p3m_kick")
     return mom
+
+
+def kick_drift(pos: torch.Tensor, mom: torch.Tensor, force: torch.Tensor, mass,
+               c_kick: float, c_drift: float, box: float):
+    """p <- p + c_kick F, then x <- wrap(x + c_drift p / m), in place, in one
+    pass (bitwise the same as kick followed by drift)."""
+    n = _vec3(pos, "pos")
+    if _vec3(mom, "mom") != n:
+        raise ValueError("mom must match pos")
+    if _vec3(force, "force", force.dtype) != n or force.dtype not in (torch.float32,
+                                                                       torch.float64):
+        raise ValueError("force must be (3, n) float32 or float64")
+    m, ms = _mass(mass, n)
+    _check(_lib.p3m_kick_drift(n, _ptr(pos), _ptr(mom), _ptr(force),
+                               1 if force.dtype == torch.float32 else 0, _ptr(m), ms,
+                               float(c_kick), float(c_drift), float(box), _stream_ptr()),
+           "p3m_kick_drift")
+    return pos, mom
 
 
 def drift_vjp(mom_bar: torch.Tensor, pos_bar: torch.Tensor, mass, c_drift: float):

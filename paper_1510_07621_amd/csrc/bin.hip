@@ -99,8 +99,11 @@ __device__ __forceinline__ int block_exclusive(int v, int* __restrict__ wsum, in
   return base + inc - v;
 }
 
+// ZERO: the input is cleared as it is read (the cell counts, so that the
+// next binning starts from zero without a fill pass).
+template <bool ZERO>
 __global__ void __launch_bounds__(kThreads)
-k_scan_tiles(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t len,
+k_scan_tiles(int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t len,
              int32_t* __restrict__ tile_sum) {
   __shared__ int wsum[kThreads / 64];
   int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -110,6 +113,11 @@ k_scan_tiles(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t 
   for (int k = 0; k < kScanItems; ++k) {
     v[k] = (base + k < len) ? in[base + k] : 0;
     local += v[k];
+  }
+  if (ZERO) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < len) in[base + k] = 0;
   }
   int total;
   int run = block_exclusive(local, wsum, total);
@@ -150,10 +158,9 @@ k_scan_add(int32_t* __restrict__ out, int64_t len, const int32_t* __restrict__ t
 
 // ---- pair-loop work list ----
 
-__global__ void k_group_chunks(const int32_t* __restrict__ start, int ng, int lg, int G,
-                               int lgG, int64_t ngroup, int32_t* __restrict__ gchunk) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ngroup) return;
+// Chunks of one i-group: its particles (G x G z-runs of G cells) over kChunk.
+__device__ __forceinline__ int group_chunks(const int32_t* __restrict__ start, int lg, int G,
+                                            int lgG, int64_t g) {
   const int lgd = lg - lgG, md = (1 << lgd) - 1;
   int gz = (int)(g & md), gy = (int)((g >> lgd) & md), gx = (int)(g >> (2 * lgd));
   int cnt = 0;
@@ -162,15 +169,34 @@ __global__ void k_group_chunks(const int32_t* __restrict__ start, int ng, int lg
       int c0 = ((((gx * G + a) << lg) | (gy * G + b)) << lg) | (gz * G);
       cnt += start[c0 + G] - start[c0];
     }
-  gchunk[g] = (cnt + kChunk - 1) / kChunk;
+  return (cnt + kChunk - 1) / kChunk;
 }
 
-__global__ void k_emit_items(const int32_t* __restrict__ gchunk,
-                             const int32_t* __restrict__ goff, int64_t ngroup,
-                             int2* __restrict__ items) {
+// Work list, pass 1: chunk counts of a tile of kThreads groups (one per
+// thread), their exclusive scan within the tile (goff) and the tile total.
+__global__ void __launch_bounds__(kThreads)
+k_items_tiles(const int32_t* __restrict__ start, int lg, int G, int lgG, int64_t ngroup,
+              int32_t* __restrict__ gchunk, int32_t* __restrict__ goff,
+              int32_t* __restrict__ tile_sum) {
+  __shared__ int wsum[kThreads / 64];
+  const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int v = g < ngroup ? group_chunks(start, lg, G, lgG, g) : 0;
+  int total;
+  const int ex = block_exclusive(v, wsum, total);
+  if (g < ngroup) {
+    gchunk[g] = v;
+    goff[g] = ex;
+  }
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// Pass 3 (after the tile sums are scanned): each group's items at its offset.
+__global__ void __launch_bounds__(kThreads)
+k_emit_items(const int32_t* __restrict__ gchunk, const int32_t* __restrict__ goff,
+             const int32_t* __restrict__ tile_off, int64_t ngroup, int2* __restrict__ items) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ngroup) return;
-  int nc = gchunk[g], o = goff[g];
+  int nc = gchunk[g], o = goff[g] + tile_off[g / kThreads];
   for (int c = 0; c < nc; ++c) items[o + c] = make_int2((int)g, c);
 }
 
@@ -179,6 +205,7 @@ inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t
 }  // namespace
 
 int scan_tmp_size(int64_t len) { return (int)((len + kScanTile - 1) / kScanTile) + 1; }
+int items_tmp_size(int64_t ngroup) { return (int)((ngroup + kThreads - 1) / kThreads) + 1; }
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -188,13 +215,17 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-// out[0..len) = exclusive scan of in[0..len); out[len] = total. tmp needs
-// scan_tmp_size(len) entries.
-hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp,
-                       hipStream_t s) {
+// out[0..len) = exclusive scan of in[0..len); out[len] = total; with
+// zero_in, in[0..len) is cleared as it is read. tmp needs scan_tmp_size(len)
+// entries.
+hipError_t launch_scan(int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hipStream_t s,
+                       bool zero_in) {
   int nt = (int)((len + kScanTile - 1) / kScanTile);
   if (nt == 0) return launch_fill_i32(out, 1, 0, s);
-  k_scan_tiles<<<nt, kThreads, 0, s>>>(in, out, len, tmp);
+  if (zero_in)
+    k_scan_tiles<true><<<nt, kThreads, 0, s>>>(in, out, len, tmp);
+  else
+    k_scan_tiles<false><<<nt, kThreads, 0, s>>>(in, out, len, tmp);
   k_scan_sums<<<1, 1024, 0, s>>>(tmp, nt, out + len);
   k_scan_add<<<nt, kThreads, 0, s>>>(out, len, tmp);
   return hipGetLastError();
@@ -204,12 +235,16 @@ hipError_t launch_bin(p3m_plan* P, int64_t n, const double* pos, const double* m
                       double mass_scalar) {
   Workspace& W = P->ws;
   hipStream_t s = P->stream;
-  hipError_t e = launch_fill_i32(W.count, P->ncell, 0, s);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  // The counts start at zero: cleared by the previous binning's scan, or
+  // here when that binning did not get as far (a failed launch)
+  if (P->count_dirty && (e = launch_fill_i32(W.count, P->ncell, 0, s)) != hipSuccess) return e;
+  P->count_dirty = 1;
   k_bin_count<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, pos, P->ng, P->lg, 1.0 / P->h,
                                                            W.key, W.rank, W.count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_scan(W.count, W.start, P->ncell, W.scan_tmp, s)) != hipSuccess) return e;
+  if ((e = launch_scan(W.count, W.start, P->ncell, W.scan_tmp, s, true)) != hipSuccess) return e;
+  P->count_dirty = 0;
   if (P->prm.precision == P3M_FP32)
     k_scatter<float><<<blocks_for(n, kThreads), kThreads, 0, s>>>(
         n, pos, mass, mass_scalar, P->ng, P->lg, P->h, W.key, W.rank, W.start, W.perm,
@@ -224,13 +259,18 @@ hipError_t launch_bin(p3m_plan* P, int64_t n, const double* pos, const double* m
 hipError_t launch_items(p3m_plan* P) {
   Workspace& W = P->ws;
   hipStream_t s = P->stream;
-  k_group_chunks<<<blocks_for(P->ngroup, kThreads), kThreads, 0, s>>>(
-      W.start, P->ng, P->lg, P->G, P->lgG, P->ngroup, W.gchunk);
+  // chunk counts + tile scans, scan of the tile sums (total to goff[ngroup]),
+  // then the items at tile offset + offset within the tile
+  const int nt = (int)((P->ngroup + kThreads - 1) / kThreads);
+  k_items_tiles<<<nt, kThreads, 0, s>>>(W.start, P->lg, P->G, P->lgG, P->ngroup, W.gchunk,
+                                        W.goff, W.scan_tmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = launch_scan(W.gchunk, W.goff, P->ngroup, W.scan_tmp, s)) != hipSuccess) return e;
+  k_scan_sums<<<1, 1024, 0, s>>>(W.scan_tmp, nt, W.goff + P->ngroup);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_emit_items<<<blocks_for(P->ngroup, kThreads), kThreads, 0, s>>>(W.gchunk, W.goff,
-                                                                    P->ngroup, W.items);
+                                                                    W.scan_tmp, P->ngroup,
+                                                                    W.items);
   return hipGetLastError();
 }
 

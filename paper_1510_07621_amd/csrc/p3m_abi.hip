@@ -586,7 +586,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   const int64_t nspec = (int64_t)q.grid_n * q.grid_n * (q.grid_n / 2 + 1);
   const size_t real = q.precision == P3M_FP32 ? sizeof(float) : sizeof(double);
   const int64_t nn = n_max > 0 ? n_max : 1;
-  P->scan_tmp_len = scan_tmp_size(P->ncell > P->ngroup ? P->ncell : P->ngroup);
+  P->scan_tmp_len = std::max(scan_tmp_size(P->ncell), items_tmp_size(P->ngroup));
 
   hipError_t err = hipGetDevice(&P->device);
   Workspace& W = P->ws;
@@ -793,6 +793,21 @@ int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,
   if (!mass && !(mass_scalar != 0 && std::isfinite(mass_scalar))) return P3M_EINVAL;
   return status_of(launch_drift(n, pos, mom, mass, mass_scalar, c_drift, box,
                                 (hipStream_t)hip_stream));
+}
+
+int p3m_kick_drift(int64_t n, double* pos, double* mom, const void* force, int32_t force_fp32,
+                   const double* mass, double mass_scalar, double c_kick, double c_drift,
+                   double box, void* hip_stream) {
+  if (n < 0) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!pos || !mom || !force || !(box > 0) || !std::isfinite(box) || !std::isfinite(c_kick) ||
+      !std::isfinite(c_drift))
+    return P3M_EINVAL;
+  if (!mass && !(mass_scalar != 0 && std::isfinite(mass_scalar))) return P3M_EINVAL;
+  const size_t vbytes = (size_t)(3 * n) * sizeof(double);
+  if (overlaps(pos, vbytes, mom, vbytes)) return P3M_EINVAL;
+  return status_of(launch_kick_drift(n, pos, mom, force, force_fp32 ? 1 : 0, mass, mass_scalar,
+                                     c_kick, c_drift, box, (hipStream_t)hip_stream));
 }
 
 int p3m_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar, const double* mass,

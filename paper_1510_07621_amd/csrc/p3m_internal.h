@@ -88,6 +88,7 @@ struct p3m_plan {
   double tab64_v0 = 0, tab64_v1 = 0;  // leading pieces evaluated exactly
   int tab64_exact = 0;
   int scan_tmp_len = 0;
+  int count_dirty = 1;          // cell counts not known to be zero (set until a binning's scan)
   p3m::Workspace ws;
   // stage timers: events [call][2 * stage + {0: start, 1: end}]
   int timing_cap = 0;           // force calls that can be recorded
@@ -101,9 +102,10 @@ namespace p3m {
 
 // Launchers (each enqueues on plan->stream; returns hipSuccess or the error).
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp,
-                       hipStream_t s);
+hipError_t launch_scan(int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hipStream_t s,
+                       bool zero_in = false);
 int scan_tmp_size(int64_t len);
+int items_tmp_size(int64_t ngroup);   // block sums of the work-list scan
 
 hipError_t launch_bin(p3m_plan* P, int64_t n, const double* pos, const double* mass,
                       double mass_scalar);
@@ -147,6 +149,9 @@ hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar
                             bool uniform_mass, void* acc_out = nullptr);
 hipError_t launch_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar,
                             const double* mass, double ms, double c, hipStream_t s);
+hipError_t launch_kick_drift(int64_t n, double* pos, double* mom, const void* force, int fp32,
+                             const double* mass, double ms, double ck, double cd, double box,
+                             hipStream_t s);
 hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,
                        hipStream_t s);
 hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double* mass,

@@ -40,7 +40,42 @@ __global__ void k_drift(int64_t n, double* __restrict__ pos, const double* __res
   pos[k] = (w >= box) ? 0.0 : w;
 }
 
+// Kick then drift in one pass over the particles (the first half of a
+// kick-drift-kick step): the same operations in the same order as k_kick
+// followed by k_drift, so the result is bitwise the same, without writing and
+// re-reading the momenta.
+template <typename F>
+__global__ void k_kick_drift(int64_t n, double* __restrict__ pos, double* __restrict__ mom,
+                             const F* __restrict__ force, const double* __restrict__ mass,
+                             double mass_scalar, double ck, double cd, double box) {
+#pragma clang fp contract(off)
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * n) return;
+  int64_t i = k % n;
+  double f = (double)force[k];
+  double p = mom[k] + ck * f;
+  mom[k] = p;
+  double m = mass ? mass[i] : mass_scalar;
+  double v = p / m;
+  double y = pos[k] + cd * v;
+  double w = y - box * floor(y / box);
+  pos[k] = (w >= box) ? 0.0 : w;
+}
+
 }  // namespace
+
+hipError_t launch_kick_drift(int64_t n, double* pos, double* mom, const void* force, int fp32,
+                             const double* mass, double ms, double ck, double cd, double box,
+                             hipStream_t s) {
+  unsigned blocks = (unsigned)((3 * n + kThreads - 1) / kThreads);
+  if (fp32)
+    k_kick_drift<float><<<blocks, kThreads, 0, s>>>(n, pos, mom, (const float*)force, mass, ms,
+                                                    ck, cd, box);
+  else
+    k_kick_drift<double><<<blocks, kThreads, 0, s>>>(n, pos, mom, (const double*)force, mass,
+                                                     ms, ck, cd, box);
+  return hipGetLastError();
+}
 
 hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,
                        hipStream_t s) {

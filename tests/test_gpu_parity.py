@@ -46,6 +46,28 @@ def test_kick_bitwise(n):
 
 
 @pytest.mark.parametrize("use_mass_array", [False, True])
+def test_kick_drift_fused_bitwise(use_mass_array):
+    """The fused first half of a KDK step equals the oracle's kick followed by
+    its drift bit for bit, for both force precisions, wrapping included."""
+    from paper_1510_07621_amd import binding
+    n = 4099                                    # not a multiple of the block
+    rng = np.random.default_rng(9)
+    x = ics.uniform(n, 1.0, seed=9)
+    p = rng.normal(size=(3, n)) * 2.0
+    m = rng.uniform(0.5, 2.0, n) if use_mass_array else 0.75
+    for fdt in (np.float64, np.float32):
+        F = rng.normal(size=(3, n)).astype(fdt)
+        xd, pd = dev(x), dev(p)
+        binding.kick_drift(xd, pd, dev(F, torch.float64 if fdt == np.float64 else torch.float32),
+                           dev(m) if use_mass_array else m, 0.37, 0.61, 1.0)
+        p1 = integrate.kick(p, F, 0.37)
+        assert np.array_equal(host(pd), p1)
+        assert np.array_equal(host(xd), integrate.drift(x, p1, m, 0.61, 1.0))
+    with pytest.raises(ValueError):
+        binding.kick_drift(dev(x), dev(p), dev(F[:, :10]), m, 0.1, 0.1, 1.0)
+
+
+@pytest.mark.parametrize("use_mass_array", [False, True])
 def test_drift_bitwise_and_wraps(use_mass_array):
     from paper_1510_07621_amd import binding
     n = 5000
