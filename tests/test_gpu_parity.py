@@ -285,6 +285,34 @@ def test_permutation_invariance():
     assert _err(Fp, F[:, perm])["rms"] < 1e-12
 
 
+def test_back_to_back_calls_without_sync_match_separate_calls():
+    """The force call forks its mesh part onto the plan's second stream and
+    joins it before its last kernel: calls queued back to back (no host
+    synchronisation in between, stage timers on) give the forces of calls
+    made one at a time, and the mesh-only and pair-only calls in between
+    still read a consistent workspace."""
+    n = 6000
+    xs = [ics.uniform(n, seed=40 + k) for k in range(3)]
+    with plan(32, n, "fp64", softening=1e-3) as P:
+        ref = []
+        for x in xs:
+            ref.append(host(P.force(dev(x), 1.0 / n)))
+        P.set_timing(8)
+        outs = [P.force(dev(x), 1.0 / n) for x in xs]
+        pm = P.pm_force(dev(xs[0]), 1.0 / n)
+        pp = P.pp_force(dev(xs[1]), 1.0 / n)
+        again = P.force(dev(xs[2]), 1.0 / n)
+        torch.cuda.synchronize()
+        ncall, st = P.stage_times()
+        pm_ref = host(P.pm_force(dev(xs[0]), 1.0 / n))
+        pp_ref = host(P.pp_force(dev(xs[1]), 1.0 / n))
+    for got, want in zip(outs + [again], ref + [ref[2]]):
+        assert _err(host(got), want)["max"] < 1e-12
+    assert _err(host(pm), pm_ref)["max"] < 1e-12
+    assert _err(host(pp), pp_ref)["max"] < 1e-12
+    assert ncall == 6 and all(v > 0 for v in st.values())
+
+
 # --------------------------------------------------------------- full-size workloads, sampled
 
 @pytest.mark.parametrize("name,precision,tol", [
