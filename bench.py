@@ -1,10 +1,11 @@
 """Throughput of the P3M gravity step on one MI355X.
 
 A step is one kick-drift-kick leapfrog step of the whole force path:
-kick(dt/2) with the force of the previous step, drift(dt), the P3M force
-(binning, CIC deposit, FFT Poisson solve, gradient + interpolation, pair
-sum, combine) and kick(dt/2), all on one HIP stream with the particles
-resident in HBM. Workload: 128^3 particles on a Zel'dovich-displaced lattice
+kick(dt/2) with the force of the previous step and drift(dt) (one fused
+pass), the P3M force (binning; then the CIC deposit and FFT Poisson solve on
+the plan's second stream beside the pair sum; then gradient + interpolation,
+which adds the two parts) and kick(dt/2), ordered on one HIP stream with the
+particles resident in HBM. Workload: 128^3 particles on a Zel'dovich-displaced lattice
 (P(k) ~ k^-2, rms displacement 0.3 spacing), 128^3 PM grid, r_s = 1.25 cells,
 r_c = 4.5 r_s, Plummer softening 0.03 spacing, G = 1, FP32 force arithmetic
 with FP64 positions, momenta, kick and drift.
@@ -30,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "zeldovich128"
 FLOP_PER_PAIR = 41          # 37 FP32 arithmetic flops + 4 transcendentals per pair
-FP32_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak (needs packed FP32)
+FP32_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak
 FP64_PEAK_TFLOPS = 78.6     # MI355X published FP64 vector peak
 HBM_PEAK_GBS = 8000.0
 
