@@ -123,7 +123,10 @@ constexpr double series_coef(int n) {
   return (n % 2 ? -1.0 : 1.0) / (fact * (2 * n + 3));
 }
 
-__device__ __forceinline__ double split_f64_series(double r2, double inv2rs) {
+// Out of line: its sixteen constants would otherwise stay in registers
+// across the whole pair loop for a branch that is rarely taken (FP64 loop
+// 128 -> 108 VGPRs, no spills, 2.5 % faster).
+__device__ __attribute__((noinline)) double split_f64_series(double r2, double inv2rs) {
   const double s = r2 * inv2rs * inv2rs;              // u^2
   double p = series_coef(kSeriesTerms - 1);
 #pragma unroll
