@@ -84,28 +84,52 @@ def _pairs(pos, box, r_c, method="auto"):
     return i[keep], j[keep], d[keep], r2[keep]
 
 
-def pp_vjp(pos, mass, box, r_s, r_c, eps, lam, G=1.0, method="auto"):
-    """pos_bar (3, N) of the short-range force m_i a_PP,i for cotangent lam (3, N)."""
+def _pairs_of(pos, targets, box, r_c):
+    """Pairs (t, j) with t indexing ``targets``: every j at minimum-image
+    distance 0 < r < r_c from particle targets[t] (periodic k-d tree)."""
+    x = np.ascontiguousarray(pos.T)
+    tg = np.asarray(targets)
+    lists = cKDTree(x, boxsize=box).query_ball_point(x[tg], r_c)
+    t = np.repeat(np.arange(tg.size), [len(l) for l in lists])
+    j = np.concatenate([np.asarray(l, dtype=np.int64) for l in lists]) if t.size else t
+    d = x[tg[t]] - x[j]
+    d -= box * np.round(d / box)
+    r2 = np.einsum("pd,pd->p", d, d)
+    keep = (r2 < r_c * r_c) & (r2 > 0.0)
+    return t[keep], j[keep], d[keep], r2[keep]
+
+
+def pp_vjp(pos, mass, box, r_s, r_c, eps, lam, G=1.0, method="auto", targets=None):
+    """pos_bar (3, N) of the short-range force m_i a_PP,i for cotangent lam (3, N);
+    with ``targets``, only those particles' columns (3, len(targets)), from
+    their own pairs."""
     pos = np.asarray(pos, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
     n = pos.shape[1]
     if not (r_c < 0.5 * box):
         raise ValueError("minimum-image pair sum needs r_c < box/2")
     m = _as_mass(mass, n)
-    i, j, d, r2 = _pairs(pos, box, r_c, method)
+    if targets is None:
+        i, j, d, r2 = _pairs(pos, box, r_c, method)
+        k, rows = i, n
+    else:
+        tg = np.asarray(targets)
+        i, j, d, r2 = _pairs_of(pos, tg, box, r_c)
+        k, rows = tg[i], tg.size
     r = np.sqrt(r2)
     rho2 = r2 + eps * eps
     f = split_factor(r, r_s)
     fp = split_factor_derivative(r, r_s)
     g = f / rho2 ** 1.5
     g_over_r = fp / (r * rho2 ** 1.5) - 3.0 * f / rho2 ** 2.5   # g'(r) / r
-    dl = lam[:, i].T - lam[:, j].T                               # (P, 3)
+    dl = lam[:, k].T - lam[:, j].T                               # (P, 3)
     rdl = np.einsum("pd,pd->p", d, dl)
     contrib = g[:, None] * dl + (g_over_r * rdl)[:, None] * d    # J (lam_k - lam_j)
     contrib *= m[j][:, None]
-    out = np.zeros((n, 3))
+    out = np.zeros((rows, 3))
     np.add.at(out, i, contrib)
-    return -G * m[None, :] * out.T
+    mk = m if targets is None else m[np.asarray(targets)]
+    return -G * mk[None, :] * out.T
 
 
 def cic_weight_gradients(pos, box, ng):

@@ -164,3 +164,19 @@ def test_p3m_vjp_and_leapfrog_vjp_match_finite_differences():
     a, b = adjoint.leapfrog_vjp(xs0, m, zero_vjp, dt, xb, pb)
     np.testing.assert_array_equal(a, xb)
     np.testing.assert_allclose(b, pb + dt / m[None, :] * xb, rtol=1e-15)
+
+
+def test_pp_vjp_on_targets_equals_the_full_columns():
+    """The target-restricted short-range transpose (each target's own pairs
+    from a k-d tree) gives the same columns as the all-pairs sum."""
+    from paper_1510_07621_amd import ics
+    rng = np.random.default_rng(6)
+    pos = ics.uniform(3000, seed=5)
+    m = rng.uniform(0.5, 1.5, 3000) / 3000
+    lam = rng.normal(size=(3, 3000))
+    r_s = 1.25 / 16
+    full = adjoint.pp_vjp(pos, m, 1.0, r_s, 4.5 * r_s, 0.002, lam)
+    tg = np.sort(rng.choice(3000, 200, replace=False))
+    part = adjoint.pp_vjp(pos, m, 1.0, r_s, 4.5 * r_s, 0.002, lam, targets=tg)
+    assert part.shape == (3, 200)
+    assert np.max(np.abs(part - full[:, tg])) <= 1e-13 * np.max(np.abs(full))
