@@ -249,3 +249,28 @@ def test_zeldovich64_kdk_gradient_matches_finite_differences():
     fd, ad = np.array(fd), np.array(ad)
     assert len(fd) >= 40
     assert np.linalg.norm(fd - ad) <= 1e-3 * np.linalg.norm(ad)
+
+
+@pytest.mark.parametrize("name,precision,tol", [
+    ("zeldovich64_kdk", "fp64", 1e-11), ("plummer128_kdk", "fp64", 1e-11),
+    ("plummer128_kdk", "fp32", 1e-4)])
+def test_full_size_force_vjp_sampled(name, precision, tol):
+    """The force adjoint at the full sizes of the two adjoint workloads, in
+    the plan configuration the bench times, against the oracle's transpose
+    on 384 sampled particles (short range from each sample's own pairs, long
+    range from the full-grid solve)."""
+    from oracle import adjoint as o_adj
+    from paper_1510_07621_amd import binding
+    w = ics.workload(name)
+    pos = w.positions()
+    lam = np.random.default_rng(81).normal(size=(3, w.n))
+    tg = np.sort(np.random.default_rng(82).choice(w.n, size=384, replace=False))
+    ref = (o_adj.pp_vjp(pos, w.mass, w.box, w.r_s, w.r_c, w.softening, lam, w.G, targets=tg) +
+           o_adj.pm_vjp(pos, w.mass, w.box, w.grid_n, w.r_s, lam, w.G)[:, tg])
+    with binding.Plan(binding.Params(grid_n=w.grid_n, box=w.box, rs_cells=w.rs_cells,
+                                     cutoff_rs=w.cutoff_rs, softening=w.softening, G=w.G,
+                                     precision=precision, adjoint=1), w.n) as P:
+        got = host(P.force_vjp(dev(pos), w.mass, dev(lam)))[:, tg]
+    e = _err(got, ref)
+    print(name, precision, e)
+    assert e <= tol
