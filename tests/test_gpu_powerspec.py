@@ -47,6 +47,21 @@ def test_power_spectrum_parity_zeldovich64(precision, tol, deconv):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-3)])
+def test_power_spectrum_parity_zeldovich128_bench_configuration(precision, tol):
+    """The full-size call the bench times: 128^3 particles, 128^3 grid, the
+    default 64 shells, sigma at 8 cells."""
+    w = ics.workload("zeldovich128")
+    pos = w.positions()
+    R = 8.0 / 128
+    ref = powerspec.power_spectrum(pos, w.mass, 1.0, 128, 64, r_tophat=R)
+    with plan(128, w.n, precision) as P:
+        k, p, m, s = P.power_spectrum(dev(pos), w.mass, r_tophat=R)
+        got = (host(k), host(p), host(m), float(host(s)))
+    assert got[1].shape == (64,)
+    _compare(got, ref, tol, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-3)])
 def test_power_spectrum_parity_clustered_masses_and_all_shells(precision, tol):
     """Plummer-clustered particles with per-particle masses on a 32^3 grid in
     a box of side 3, every shell out to the grid's corner, and R = 0 (the
