@@ -24,13 +24,16 @@ namespace {
 
 using namespace brick;
 
+// In input order (coalesced reads of the three cotangent rows); each particle
+// goes to its sorted slot start[key] + rank, as in the binning's scatter.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_lambda_sort(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ fbar,
+k_lambda_sort(int64_t n, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
+              const int32_t* __restrict__ start, const double* __restrict__ fbar,
               typename Vec<T>::v4* __restrict__ lam) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int64_t i = perm[s];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = start[key[i]] + rank[i];
   typename Vec<T>::v4 o;
   o.x = (T)fbar[i];
   o.y = (T)fbar[n + i];
@@ -176,7 +179,7 @@ unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 template <typename T>
 hipError_t launch_lambda_sort(p3m_plan* P, int64_t n, const double* force_bar) {
   k_lambda_sort<T><<<blocks_of(n, 256), 256, 0, P->stream>>>(
-      n, P->ws.perm, force_bar, (typename Vec<T>::v4*)P->ws.lam);
+      n, P->ws.key, P->ws.rank, P->ws.start, force_bar, (typename Vec<T>::v4*)P->ws.lam);
   return hipGetLastError();
 }
 
