@@ -81,11 +81,14 @@ struct PairArgs {
   // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
   const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
-  float rho_e2, rho_cut2;               // tab_e2 / tab_s2 and r_c^2 + rho_e2
+  // FP32 force over the softened-distance table: positions scaled by s,
+  // so rho^2 starts from tab_e2 and is tested against s^2 r_c^2 + tab_e2
+  float rho_e2, rho_cut2;
   double rho_cut2d;                     // FP64: r_c^2 + eps^2
   double tab_s64, tab_off64;            // FP64 table: x = s v - s v0 (v = r or rho)
   int tab_exact;                        // FP64: leading pieces evaluated exactly
   double wscale;                        // -G, times s^3 on the FP32 path
+  double wscale_rho;                    // -G s^2: FP32 force on scaled positions
   // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
   // pair Hessian (see pair_vjp_weights)
   const typename Vec<T>::v4* __restrict__ lam;
@@ -184,10 +187,10 @@ __device__ __forceinline__ float pair_weight(float r2, const PairArgs<float>& A,
   return f * (inv * inv * inv);
 }
 
-// The same weight from rho^2 = r^2 + eps^2 (floored as above): q = s^2 rho^2.
-__device__ __forceinline__ float pair_weight_rho(float rho2, const PairArgs<float>& A,
+// The same weight from q = s^2 (r^2 + eps^2) (floored as above), formed from
+// positions already scaled by s.
+__device__ __forceinline__ float pair_weight_rho(float q, const PairArgs<float>& A,
                                                  const SplitTable<float>& tab) {
-  const float q = rho2 * A.tab_s2;
   const float inv = __builtin_amdgcn_rsqf(q);
   const float x = __builtin_fmaf(q, inv, -A.tab_off);
   const int k = (int)x;
@@ -382,7 +385,18 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   constexpr int kCap = Stage<T, VJP>::kCap, kStage = Stage<T, VJP>::kPer;
   const int lane = threadIdx.x;
   const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
+  // The FP32 force over the softened-distance table runs on positions
+  // scaled by the table's s (one multiply fewer per evaluated pair). An i
+  // and its own staged copy must come out bit-identical (the self pair's
+  // separation is exactly zero), so both are formed by the same fma and then
+  // the same multiply.
+  constexpr bool SC = sizeof(T) == 4 && TAB == 1 && !COUNT && !VJP;
   const T h = A.h;
+  const T ps = T(A.tab_s);
+  auto coord = [&](int cell, T off) {
+    const T v = fma(T(cell), h, off);
+    return SC ? v * ps : v;
+  };
   const int nu = (ni + U - 1) / U;      // slot sets
   const int ns = min(64 / nu, kStreams);  // streams
   const int il = lane % nu, st = lane / nu;
@@ -401,9 +415,9 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
     si[u] = S.i_lo[run] + (fi - S.i_pre[run]);
     const T4 pi = A.rec[si[u]];
     const int czi = A.skey[si[u]] & mask;
-    xi[u] = has ? T(run >> lgG) * h + pi.x : T(kFar);
-    yi[u] = has ? T(run & (G - 1)) * h + pi.y : T(kFar);
-    zi[u] = has ? T(czi - gz0) * h + pi.z : T(kFar);
+    xi[u] = has ? coord(run >> lgG, pi.x) : T(kFar);
+    yi[u] = has ? coord(run & (G - 1), pi.y) : T(kFar);
+    zi[u] = has ? coord(czi - gz0, pi.z) : T(kFar);
     ax[u] = ay[u] = az[u] = T(0);
     if constexpr (VJP) {
       const T4 li = A.lam[si[u]];
@@ -497,9 +511,9 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
           if (src[e] >= 0) {
             const int d = dd[e];
             T4 o;
-            o.x = T(S.d_rx[d / 3]) * h + pj[e].x;
-            o.y = T(S.d_ry[d / 3]) * h + pj[e].y;
-            o.z = T(cz[e] + S.d_zs[d]) * h + pj[e].z;
+            o.x = coord(S.d_rx[d / 3], pj[e].x);
+            o.y = coord(S.d_ry[d / 3], pj[e].y);
+            o.z = coord(cz[e] + S.d_zs[d], pj[e].z);
             o.w = pj[e].w;
             S.jb[q0 + e] = o;
             if constexpr (VJP) S.jl[q0 + e] = lj[e];
@@ -549,6 +563,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
       // RHO (force over the softened-distance table): the squared separation
       // is accumulated on top of eps^2, so the test compares
       // rho^2 = r^2 + eps^2 with r_c^2 + eps^2 and the weight starts from rho^2
+      // (FP32: all of it in the scaled units)
       constexpr bool RHO = TAB == 1 && !COUNT;
       const T e2r = sizeof(T) == 4 ? T(A.rho_e2) : A.eps2;
       const T cut2 = RHO ? (sizeof(T) == 4 ? T(A.rho_cut2) : T(A.rho_cut2d)) : A.rc2;
@@ -630,7 +645,8 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
     while (run + 1 < GG && S.i_pre[run + 1] <= fi) ++run;
     const int s = S.i_lo[run] + (fi - S.i_pre[run]);
     const double m = (double)A.rec[s].w;
-    double gx = A.wscale * (double)sx, gy = A.wscale * (double)sy, gz = A.wscale * (double)sz;
+    const double ws = SC ? A.wscale_rho : A.wscale;
+    double gx = ws * (double)sx, gy = ws * (double)sy, gz = ws * (double)sz;
     if (UM) {
       gx *= m; gy *= m; gz *= m;
     }
@@ -750,8 +766,9 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.tab_s2 = (float)(s * s);
     A.tab_e2 = (float)std::max(s * s * P->eps * P->eps, 1e-12);
     A.tab_off = (float)(s * P->tab_v0);
-    A.rho_e2 = (float)(std::max(s * s * P->eps * P->eps, 1e-12) / (s * s));
-    A.rho_cut2 = (float)(P->r_c * P->r_c + (double)A.rho_e2);
+    A.rho_e2 = A.tab_e2;
+    A.rho_cut2 = (float)(s * s * P->r_c * P->r_c + (double)A.tab_e2);
+    A.wscale_rho = A.wscale * s * s;
     A.wscale *= s * s * s;
     A.vjp_k5 = (T)(3.0 * s * s);
     A.vjp_s = (T)(s * s);

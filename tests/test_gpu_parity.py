@@ -213,6 +213,43 @@ def test_empty_and_single_particle():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("box", [1.0, 2.7])
+@pytest.mark.parametrize("soft_cells", [0.0, 0.03, 0.3])
+def test_lone_particle_short_range_force_is_exactly_zero(precision, box, soft_cells):
+    """A particle alone in the box meets only itself: the pair loop must see
+    a separation of exactly zero between it and its own staged copy (the
+    i-side and j-side relative coordinates formed identically), for cell
+    sizes that are and are not powers of two and for both table variables;
+    any rounding gap would give it a self-force through the softened weight."""
+    grid = 16
+    h = box / grid
+    for where in ([0.3, 0.7, 0.11], [0.0, 0.5, 0.99999], [0.51, 0.02, 0.73]):
+        one = dev(np.array(where)[:, None] * box)
+        with plan(grid, 4, precision, box=box, softening=soft_cells * h) as P:
+            F = host(P.pp_force(one, 1.7))
+        assert np.array_equal(F, np.zeros((3, 1))), (where, F)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_pp_force_parity_box_not_a_power_of_two(precision, tol):
+    """The short-range sum in a box of side 2.7 (cell size not a power of
+    two), default softening, with close pairs, against the oracle."""
+    grid, box = 16, 2.7
+    h = box / grid
+    rng = np.random.default_rng(41)
+    base = ics.uniform(3500, box, seed=42)
+    near = (base[:, :300] + rng.uniform(0.05, 0.2, (3, 300)) * h) % box
+    pos = np.concatenate([base, near], axis=1)
+    eps = 0.03 * h
+    m = 1.0 / pos.shape[1]
+    ref = o_pp.pp_accel(pos, m, box, 1.25 * h, 4.5 * 1.25 * h, eps, 1.0) * m
+    with plan(grid, pos.shape[1], precision, box=box, softening=eps) as P:
+        F = host(P.pp_force(dev(pos), m))
+    e = _err(F, ref)
+    assert e["rms"] <= tol, e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_dense_cell_ragged_and_masses(precision):
     """300 particles in one cell (several 64-particle chunks), plus a ragged
     uniform background; per-particle masses; compared with the oracle."""
