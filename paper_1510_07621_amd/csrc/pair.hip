@@ -81,14 +81,16 @@ struct PairArgs {
   // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
   const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
-  // FP32 force over the softened-distance table: positions scaled by s,
-  // so rho^2 starts from tab_e2 and is tested against s^2 r_c^2 + tab_e2
+  // Force over the softened-distance table: positions scaled by s, so
+  // rho^2 starts from (s eps)^2 and is tested against s^2 (r_c^2 + eps^2).
+  // FP32 (from tab_e2, floored):
   float rho_e2, rho_cut2;
-  double rho_cut2d;                     // FP64: r_c^2 + eps^2
+  double rho_e2d, rho_cut2d;            // FP64
+  double rho_inv2rs;                    // FP64: 1 / (2 r_s s), for the series
   double tab_s64, tab_off64;            // FP64 table: x = s v - s v0 (v = r or rho)
   int tab_exact;                        // FP64: leading pieces evaluated exactly
   double wscale;                        // -G, times s^3 on the FP32 path
-  double wscale_rho;                    // -G s^2: FP32 force on scaled positions
+  double wscale_rho;                    // -G s^2: force on scaled positions
   // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
   // pair Hessian (see pair_vjp_weights)
   const typename Vec<T>::v4* __restrict__ lam;
@@ -208,24 +210,26 @@ __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>&
   return r2 > 0.0 ? f * (inv * inv * inv) : 0.0;   // eps may be 0
 }
 
-// The same weight (softened-distance table) from rho^2 = r^2 + eps^2; r^2
-// itself is formed only for the series pieces. A pair whose rho^2 rounds to
-// eps^2 (the self pair) gets weight 0.
+// The same weight (softened-distance table) from q = s^2 (r^2 + eps^2),
+// formed from positions already scaled by s, so the bin coordinate is
+// q rsqrt(q) - s v0 and the weight f / (s rho)^3; r^2 itself is formed only
+// for the series pieces. A pair whose q rounds to (s eps)^2 (the self pair)
+// gets weight 0.
 __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<double>& A,
                                                   const SplitTable<double>& tab) {
   const double inv = rsqrt_pos(q);
-  const double x = fma(q * inv, A.tab_s64, -A.tab_off64);
+  const double x = fma(q, inv, -A.tab_off64);
   const int k = min(max((int)x, 0), kSplitBins);
   double f;
   if (k < A.tab_exact) {
-    f = split_f64_series(fmax(q - A.eps2, 0.0), A.inv2rs);
+    f = split_f64_series(fmax(q - A.rho_e2d, 0.0), A.rho_inv2rs);
   } else {
     const double t = __builtin_amdgcn_fract(x);
     f = tab.c[kSplitCoef64 - 1][k];
 #pragma unroll
     for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * t + tab.c[l][k];
   }
-  return q > A.eps2 ? f * (inv * inv * inv) : 0.0;
+  return q > A.rho_e2d ? f * (inv * inv * inv) : 0.0;
 }
 
 // Adjoint weights of a pair: with g = f / rho^3 and the pair Jacobian
@@ -385,14 +389,14 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   constexpr int kCap = Stage<T, VJP>::kCap, kStage = Stage<T, VJP>::kPer;
   const int lane = threadIdx.x;
   const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
-  // The FP32 force over the softened-distance table runs on positions
-  // scaled by the table's s (one multiply fewer per evaluated pair). An i
+  // The force over the softened-distance table runs on positions scaled by
+  // the table's s (the bin coordinate then needs no extra multiply). An i
   // and its own staged copy must come out bit-identical (the self pair's
   // separation is exactly zero), so both are formed by the same fma and then
   // the same multiply.
-  constexpr bool SC = sizeof(T) == 4 && TAB == 1 && !COUNT && !VJP;
+  constexpr bool SC = TAB == 1 && !COUNT && !VJP;
   const T h = A.h;
-  const T ps = T(A.tab_s);
+  const T ps = sizeof(T) == 4 ? T(A.tab_s) : T(A.tab_s64);
   auto coord = [&](int cell, T off) {
     const T v = fma(T(cell), h, off);
     return SC ? v * ps : v;
@@ -565,7 +569,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
       // rho^2 = r^2 + eps^2 with r_c^2 + eps^2 and the weight starts from rho^2
       // (FP32: all of it in the scaled units)
       constexpr bool RHO = TAB == 1 && !COUNT;
-      const T e2r = sizeof(T) == 4 ? T(A.rho_e2) : A.eps2;
+      const T e2r = sizeof(T) == 4 ? T(A.rho_e2) : T(A.rho_e2d);
       const T cut2 = RHO ? (sizeof(T) == 4 ? T(A.rho_cut2) : T(A.rho_cut2d)) : A.rc2;
       // FP64 reads the next staged j while the current one is tested
       // (measured 3 % faster; FP32 gains nothing and spills more)
@@ -749,7 +753,6 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.h = (T)P->h;
   A.rc2 = (T)(P->r_c * P->r_c);
   A.eps2 = (T)(P->eps * P->eps);
-  A.rho_cut2d = P->r_c * P->r_c + P->eps * P->eps;
   A.inv2rs = (T)(1.0 / (2.0 * P->r_s));
   A.wscale = -P->prm.G;
   if constexpr (sizeof(T) == 8) {
@@ -757,6 +760,10 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.split_tab = W.split_tab64;
     A.tab_s64 = s;
     A.tab_off64 = s * P->tab64_v0;
+    A.rho_e2d = s * s * P->eps * P->eps;
+    A.rho_cut2d = s * s * (P->r_c * P->r_c + P->eps * P->eps);
+    A.rho_inv2rs = 1.0 / (2.0 * P->r_s * s);
+    A.wscale_rho = -P->prm.G * s * s;
     A.tab_exact = P->tab64_exact;
   }
   if constexpr (sizeof(T) == 4) {
