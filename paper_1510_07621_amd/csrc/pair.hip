@@ -91,10 +91,12 @@ struct PairArgs {
   int tab_exact;                        // FP64: leading pieces evaluated exactly
   double wscale;                        // -G, times s^3 on the FP32 path
   double wscale_rho;                    // -G s^2: force on scaled positions
+  double wscale_vjp;                    // -G s^3: adjoint on scaled positions
+  T rc2s;                               // s^2 r_c^2: cutoff on scaled positions
   // adjoint mode: sorted cotangent (x, y, z, -) and the constants of the
   // pair Hessian (see pair_vjp_weights)
   const typename Vec<T>::v4* __restrict__ lam;
-  T vjp_ce, vjp_k5, vjp_e2, vjp_s;
+  T vjp_ce, vjp_k5, vjp_e2, vjp_ce_s;   // vjp_ce_s = vjp_ce / s^3
   const typename Vec<T>::v4* __restrict__ acc_pm;  // sorted PM acceleration or null
   typename Vec<T>::v4* __restrict__ acc_out;       // sorted output acceleration or null
   const int32_t* __restrict__ perm;
@@ -241,32 +243,42 @@ __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<doubl
 // both at the cutoff); the FP64 leading pieces evaluated exactly take
 // d = -r e^{-u^2} / (2 sqrt(pi) r_s^3) with e^{-u^2} from its series. Over r
 // (TAB 0, wide softening) d comes from that formula with the library
-// exponential. FP32 in the scaled units of pair_weight: rsq(q) = 1 / (s rho),
-// the common factor s^3 folded into wscale, vjp_k5 = 3 s^2, vjp_s = s^2;
-// FP64: physical units, vjp_k5 = 3, vjp_s = s.
+// exponential.
+// Units. TAB 1 works on positions scaled by s (r2 = s^2 r^2): with
+// inv = 1 / (s rho) the returned w1 = f inv^3 and w2 = inv^3 (ft inv - 3 f
+// inv^2) (ft the piece's t-derivative) are g / s^3 and (g'(r)/r) / s^5, so
+// J dl = s^3 (w1 dl + w2 (r_s . dl) r_s) with r_s the scaled separation; the
+// s^3 sits in wscale_vjp. TAB 0 works on physical positions: FP32 in the
+// scaled units of pair_weight (rsq(q) = 1 / (s rho), s^3 folded into wscale,
+// vjp_k5 = 3 s^2); FP64 in physical units (vjp_k5 = 3).
 template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>& A,
                                                  const SplitTable<float>& tab, float& w1,
                                                  float& w2) {
-  const float q = __builtin_fmaf(r2, A.tab_s2, A.tab_e2);
+  const float q = TAB ? r2 + A.tab_e2 : __builtin_fmaf(r2, A.tab_s2, A.tab_e2);
   const float inv = __builtin_amdgcn_rsqf(q);
   const float x = TAB ? __builtin_fmaf(q, inv, -A.tab_off)
                       : __builtin_amdgcn_sqrtf(r2) * A.tab_s;
   const int k = (int)x;
   const float t = __builtin_amdgcn_fractf(x);
-  const float c1 = tab.c[1][k], c2 = tab.c[2][k], c3 = tab.c[3][k];
-  const float f = tab.c[0][k] + t * (c1 + t * (c2 + t * c3));
   const float inv2 = inv * inv, inv3 = inv2 * inv;
-  float d;
-  if constexpr (TAB == 1) {
-    const float ft = __builtin_fmaf(t, __builtin_fmaf(3.f * t, c3, c2 + c2), c1);
-    d = A.vjp_s * ft * inv;
-  } else {
-    d = -A.vjp_ce * __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_exp2f(r2 * A.vjp_e2);
-  }
   const bool pos = r2 > 0.f;            // self pairs: zero, never inf * 0
-  w1 = pos ? f * inv3 : 0.f;
-  w2 = pos ? inv3 * (d - A.vjp_k5 * f * inv2) : 0.f;
+  if constexpr (TAB == 1) {
+    // the cubic and its t-derivative together (Horner on both)
+    float f = tab.c[3][k], ft = f;
+    f = __builtin_fmaf(f, t, tab.c[2][k]);
+    ft = __builtin_fmaf(ft, t, f);
+    f = __builtin_fmaf(f, t, tab.c[1][k]);
+    ft = __builtin_fmaf(ft, t, f);
+    f = __builtin_fmaf(f, t, tab.c[0][k]);
+    w1 = pos ? f * inv3 : 0.f;
+    w2 = pos ? inv3 * (ft * inv - 3.f * f * inv2) : 0.f;
+  } else {
+    const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
+    const float d = -A.vjp_ce * __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_exp2f(r2 * A.vjp_e2);
+    w1 = pos ? f * inv3 : 0.f;
+    w2 = pos ? inv3 * (d - A.vjp_k5 * f * inv2) : 0.f;
+  }
 }
 
 // e^{-s}, 0 <= s <= 0.81 (u <= 0.9), from its series: 19 terms leave less
@@ -282,17 +294,17 @@ template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<double>& A,
                                                  const SplitTable<double>& tab, double& w1,
                                                  double& w2) {
-  const double q = r2 + A.eps2;
+  const double q = r2 + (TAB ? A.rho_e2d : A.eps2);
   const double inv = rsqrt_pos(q);
   const double inv2 = inv * inv, inv3 = inv2 * inv;
   double f, d;
-  if constexpr (TAB == 1) {
-    const double x = fma(q * inv, A.tab_s64, -A.tab_off64);
+  if constexpr (TAB == 1) {             // scaled positions
+    const double x = fma(q, inv, -A.tab_off64);
     const int k = min(max((int)x, 0), kSplitBins);
     if (k < A.tab_exact) {              // next to the kink at r = 0: rare
-      const double u2 = r2 * A.inv2rs * A.inv2rs;
-      f = split_f64_series(r2, A.inv2rs);
-      d = -A.vjp_ce * (r2 * rsqrt_pos(r2)) * exp_neg_series(u2);
+      const double u2 = r2 * A.rho_inv2rs * A.rho_inv2rs;
+      f = split_f64_series(r2, A.rho_inv2rs);
+      d = -A.vjp_ce_s * (r2 * rsqrt_pos(r2)) * exp_neg_series(u2);
     } else {
       const double t = __builtin_amdgcn_fract(x);
       double ft = 0.0;
@@ -302,7 +314,7 @@ __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<doubl
         ft = fma(ft, t, f);
         f = fma(f, t, tab.c[l][k]);
       }
-      d = A.vjp_s * ft * inv;
+      d = ft * inv;
     }
   } else {
     const double r = sqrt(r2);
@@ -394,7 +406,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   // and its own staged copy must come out bit-identical (the self pair's
   // separation is exactly zero), so both are formed by the same fma and then
   // the same multiply.
-  constexpr bool SC = TAB == 1 && !COUNT && !VJP;
+  constexpr bool SC = TAB == 1 && !COUNT;
   const T h = A.h;
   const T ps = sizeof(T) == 4 ? T(A.tab_s) : T(A.tab_s64);
   auto coord = [&](int cell, T off) {
@@ -547,7 +559,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
           for (int u = 0; u < U; ++u) {
             const T dx = xi[u] - pj.x, dy = yi[u] - pj.y, dz = zi[u] - pj.z;
             const T r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < A.rc2) {
+            if (r2 < (SC ? A.rc2s : A.rc2)) {
               T w1, w2;
               pair_vjp_weights<TAB>(r2, A, S.tab, w1, w2);
               const T lx = lxi[u] - lj.x, ly = lyi[u] - lj.y, lz = lzi[u] - lj.z;
@@ -649,7 +661,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
     while (run + 1 < GG && S.i_pre[run + 1] <= fi) ++run;
     const int s = S.i_lo[run] + (fi - S.i_pre[run]);
     const double m = (double)A.rec[s].w;
-    const double ws = SC ? A.wscale_rho : A.wscale;
+    const double ws = !SC ? A.wscale : (VJP ? A.wscale_vjp : A.wscale_rho);
     double gx = ws * (double)sx, gy = ws * (double)sy, gz = ws * (double)sz;
     if (UM) {
       gx *= m; gy *= m; gz *= m;
@@ -764,6 +776,8 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.rho_cut2d = s * s * (P->r_c * P->r_c + P->eps * P->eps);
     A.rho_inv2rs = 1.0 / (2.0 * P->r_s * s);
     A.wscale_rho = -P->prm.G * s * s;
+    A.wscale_vjp = -P->prm.G * s * s * s;
+    A.rc2s = s * s * P->r_c * P->r_c;
     A.tab_exact = P->tab64_exact;
   }
   if constexpr (sizeof(T) == 4) {
@@ -776,15 +790,19 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.rho_e2 = A.tab_e2;
     A.rho_cut2 = (float)(s * s * P->r_c * P->r_c + (double)A.tab_e2);
     A.wscale_rho = A.wscale * s * s;
+    A.wscale_vjp = A.wscale * s * s * s;
+    A.rc2s = (float)(s * s * P->r_c * P->r_c);
     A.wscale *= s * s * s;
     A.vjp_k5 = (T)(3.0 * s * s);
-    A.vjp_s = (T)(s * s);
     A.vjp_e2 = (T)(-1.4426950408889634 / (4.0 * P->r_s * P->r_s));
   } else {
     A.vjp_k5 = T(3);
-    A.vjp_s = (T)(kSplitBins / (P->tab64_v1 - P->tab64_v0));
   }
-  A.vjp_ce = (T)(1.0 / (2.0 * 1.7724538509055160 * P->r_s * P->r_s * P->r_s));
+  const double ce = 1.0 / (2.0 * 1.7724538509055160 * P->r_s * P->r_s * P->r_s);
+  const double s_tab = sizeof(T) == 4 ? kSplitBins / (P->tab_v1 - P->tab_v0)
+                                      : kSplitBins / (P->tab64_v1 - P->tab64_v0);
+  A.vjp_ce = (T)ce;
+  A.vjp_ce_s = (T)(ce / (s_tab * s_tab * s_tab));
   A.perm = W.perm;
   A.n = n;
   return A;
