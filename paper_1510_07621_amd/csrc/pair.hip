@@ -82,9 +82,9 @@ struct PairArgs {
   const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
   // Force over the softened-distance table: positions scaled by s, so
-  // rho^2 starts from (s eps)^2 and is tested against s^2 (r_c^2 + eps^2).
-  // FP32 (from tab_e2, floored):
-  float rho_e2, rho_cut2;
+  // rho^2 starts from e2 = (s eps)^2 (floored: FP32 at tab_e2's 1e-12, FP64
+  // at 1e-200) and is tested against s^2 r_c^2 + e2.
+  float rho_e2, rho_cut2;               // FP32
   double rho_e2d, rho_cut2d;            // FP64
   double rho_inv2rs;                    // FP64: 1 / (2 r_s s), for the series
   double tab_s64, tab_off64;            // FP64 table: x = s v - s v0 (v = r or rho)
@@ -215,13 +215,16 @@ __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>&
 // The same weight (softened-distance table) from q = s^2 (r^2 + eps^2),
 // formed from positions already scaled by s, so the bin coordinate is
 // q rsqrt(q) - s v0 and the weight f / (s rho)^3; r^2 itself is formed only
-// for the series pieces. A pair whose q rounds to (s eps)^2 (the self pair)
-// gets weight 0.
+// for the series pieces. q starts from (s eps)^2 floored at 1e-200, so the
+// weight is finite for every pair (at most 1e300) and a self or coincident
+// pair contributes it times a zero separation. The bin coordinate lies in
+// [0, kSplitBins] without clamping: the table starts a hair below s eps and
+// the cutoff test bounds q by s^2 (r_c^2 + eps^2), its end.
 __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<double>& A,
                                                   const SplitTable<double>& tab) {
   const double inv = rsqrt_pos(q);
   const double x = fma(q, inv, -A.tab_off64);
-  const int k = min(max((int)x, 0), kSplitBins);
+  const int k = (int)x;
   double f;
   if (k < A.tab_exact) {
     f = split_f64_series(fmax(q - A.rho_e2d, 0.0), A.rho_inv2rs);
@@ -231,7 +234,7 @@ __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<doubl
 #pragma unroll
     for (int l = kSplitCoef64 - 2; l >= 0; --l) f = f * t + tab.c[l][k];
   }
-  return q > A.rho_e2d ? f * (inv * inv * inv) : 0.0;
+  return f * (inv * inv * inv);
 }
 
 // Adjoint weights of a pair: with g = f / rho^3 and the pair Jacobian
@@ -298,9 +301,9 @@ __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<doubl
   const double inv = rsqrt_pos(q);
   const double inv2 = inv * inv, inv3 = inv2 * inv;
   double f, d;
-  if constexpr (TAB == 1) {             // scaled positions
+  if constexpr (TAB == 1) {             // scaled positions; x in [0, kSplitBins]
     const double x = fma(q, inv, -A.tab_off64);
-    const int k = min(max((int)x, 0), kSplitBins);
+    const int k = (int)x;
     if (k < A.tab_exact) {              // next to the kink at r = 0: rare
       const double u2 = r2 * A.rho_inv2rs * A.rho_inv2rs;
       f = split_f64_series(r2, A.rho_inv2rs);
@@ -772,8 +775,8 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.split_tab = W.split_tab64;
     A.tab_s64 = s;
     A.tab_off64 = s * P->tab64_v0;
-    A.rho_e2d = s * s * P->eps * P->eps;
-    A.rho_cut2d = s * s * (P->r_c * P->r_c + P->eps * P->eps);
+    A.rho_e2d = std::max(s * s * P->eps * P->eps, 1e-200);
+    A.rho_cut2d = s * s * P->r_c * P->r_c + A.rho_e2d;
     A.rho_inv2rs = 1.0 / (2.0 * P->r_s * s);
     A.wscale_rho = -P->prm.G * s * s;
     A.wscale_vjp = -P->prm.G * s * s * s;
