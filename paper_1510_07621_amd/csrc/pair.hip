@@ -254,6 +254,8 @@ __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<doubl
 // s^3 sits in wscale_vjp. TAB 0 works on physical positions: FP32 in the
 // scaled units of pair_weight (rsq(q) = 1 / (s rho), s^3 folded into wscale,
 // vjp_k5 = 3 s^2); FP64 in physical units (vjp_k5 = 3).
+// Called only for 0 < r2 < r_c^2: the pair loop's test excludes coincident
+// particles (their pairs contribute nothing), so the weights need no guard.
 template <int TAB>
 __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>& A,
                                                  const SplitTable<float>& tab, float& w1,
@@ -265,7 +267,6 @@ __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>
   const int k = (int)x;
   const float t = __builtin_amdgcn_fractf(x);
   const float inv2 = inv * inv, inv3 = inv2 * inv;
-  const bool pos = r2 > 0.f;            // self pairs: zero, never inf * 0
   if constexpr (TAB == 1) {
     // the cubic and its t-derivative together (Horner on both)
     float f = tab.c[3][k], ft = f;
@@ -274,13 +275,13 @@ __device__ __forceinline__ void pair_vjp_weights(float r2, const PairArgs<float>
     f = __builtin_fmaf(f, t, tab.c[1][k]);
     ft = __builtin_fmaf(ft, t, f);
     f = __builtin_fmaf(f, t, tab.c[0][k]);
-    w1 = pos ? f * inv3 : 0.f;
-    w2 = pos ? inv3 * (ft * inv - 3.f * f * inv2) : 0.f;
+    w1 = f * inv3;
+    w2 = inv3 * (ft * inv - 3.f * f * inv2);
   } else {
     const float f = tab.c[0][k] + t * (tab.c[1][k] + t * (tab.c[2][k] + t * tab.c[3][k]));
     const float d = -A.vjp_ce * __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_exp2f(r2 * A.vjp_e2);
-    w1 = pos ? f * inv3 : 0.f;
-    w2 = pos ? inv3 * (d - A.vjp_k5 * f * inv2) : 0.f;
+    w1 = f * inv3;
+    w2 = inv3 * (d - A.vjp_k5 * f * inv2);
   }
 }
 
@@ -310,10 +311,11 @@ __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<doubl
       d = -A.vjp_ce_s * (r2 * rsqrt_pos(r2)) * exp_neg_series(u2);
     } else {
       const double t = __builtin_amdgcn_fract(x);
-      double ft = 0.0;
       f = tab.c[kSplitCoef64 - 1][k];
+      double ft = f;                    // the piece and its t-derivative by Horner
+      f = fma(f, t, tab.c[kSplitCoef64 - 2][k]);
 #pragma unroll
-      for (int l = kSplitCoef64 - 2; l >= 0; --l) {
+      for (int l = kSplitCoef64 - 3; l >= 0; --l) {
         ft = fma(ft, t, f);
         f = fma(f, t, tab.c[l][k]);
       }
@@ -325,9 +327,8 @@ __device__ __forceinline__ void pair_vjp_weights(double r2, const PairArgs<doubl
     f = split_f64<TAB>(r2, q, inv, A, tab);
     d = -A.vjp_ce * r * exp(-u * u);
   }
-  const bool pos = r2 > 0.0;                      // eps may be 0
-  w1 = pos ? f * inv3 : 0.0;
-  w2 = pos ? inv3 * (d - A.vjp_k5 * f * inv2) : 0.0;
+  w1 = f * inv3;
+  w2 = inv3 * (d - A.vjp_k5 * f * inv2);
 }
 
 __device__ __forceinline__ int wave_inclusive(int v) {
@@ -562,7 +563,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
           for (int u = 0; u < U; ++u) {
             const T dx = xi[u] - pj.x, dy = yi[u] - pj.y, dz = zi[u] - pj.z;
             const T r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < (SC ? A.rc2s : A.rc2)) {
+            if (r2 < (SC ? A.rc2s : A.rc2) && r2 > T(0)) {   // coincident: nothing
               T w1, w2;
               pair_vjp_weights<TAB>(r2, A, S.tab, w1, w2);
               const T lx = lxi[u] - lj.x, ly = lyi[u] - lj.y, lz = lzi[u] - lj.z;
