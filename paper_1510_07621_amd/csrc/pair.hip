@@ -23,7 +23,9 @@
 // runs' particles into LDS (kPairCap at a time) as positions relative to the
 // group's first cell, carrying the periodic shift of the run. Positions are
 // rebuilt from cell-relative offsets and small integer cell differences, so
-// the FP32 path never subtracts two large coordinates.
+// the FP32 path never subtracts two large coordinates. Over the
+// softened-distance table they are kept in the table's units (times s), so
+// the squared separation is the table's argument as it stands.
 //
 // Arithmetic. FP32: rsq(r^2 + eps^2) and f from a table of 64 cubic pieces
 // held in LDS, fitted in FP64 by the plan at the Chebyshev points of each
@@ -31,10 +33,11 @@
 // sqrt(r^2 + eps^2), which rsq already yields, so a pair costs a single
 // transcendental; when eps is too large against a piece for the cubic to
 // follow the kink at r = 0, the plan tabulates over r and a square root is
-// added. FP64: the device library's rsqrt, and f from 64 pieces of degree 6
-// (fitted in extended precision at the Chebyshev points of each piece; error
-// at FP64 rounding) over the softened distance as well, with the few pieces
-// next to the kink evaluated exactly; or over r, with a square root.
+// added. FP64: the hardware rsqrt refined by one third-order step, and f
+// from 64 pieces of degree 6 (fitted in extended precision at the Chebyshev
+// points of each piece; error at FP64 rounding) over the softened distance
+// as well, with the few pieces next to the kink evaluated exactly; or over r,
+// with a square root.
 #include <algorithm>
 
 #include "p3m_internal.h"
@@ -79,7 +82,7 @@ struct PairArgs {
   // length, q = s^2 (r^2 + eps^2), the bin coordinate is x = q rsq(q) - s v0
   // (softened variable) or x = s r (plain r), and the returned weight is
   // f rsq(q)^3 = f / (s^3 (r^2 + eps^2)^(3/2)).
-  const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [8][kSplitBins + 1]
+  const T* __restrict__ split_tab;      // FP32 [4][kSplitBins + 1], FP64 [7][kSplitBins + 1]
   float tab_s, tab_s2, tab_e2, tab_off;
   // Force over the softened-distance table: positions scaled by s, so
   // rho^2 starts from e2 = (s eps)^2 (floored: FP32 at tab_e2's 1e-12, FP64
