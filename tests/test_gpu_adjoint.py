@@ -70,6 +70,33 @@ def test_force_vjp_parity(case, precision, tol):
     assert _err(got, pp + pm) <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+@pytest.mark.parametrize("soft_cells", [0.0, 0.03])
+def test_coincident_particles_contribute_nothing(precision, tol, soft_cells):
+    """Exact duplicates of 60 particles: a pair at zero separation adds
+    nothing to the short-range force or to its adjoint (the oracle skips such
+    pairs), with and without softening; everything else matches the oracle
+    and no value is inf or NaN."""
+    from oracle import pp as o_pp
+    rng = np.random.default_rng(61)
+    base = ics.uniform(1500, seed=62)
+    pos = np.concatenate([base, base[:, :60]], axis=1)
+    n = pos.shape[1]
+    m = rng.uniform(0.5, 1.5, n) / n
+    lam = rng.normal(size=(3, n))
+    eps = soft_cells * H
+    r_s = 1.25 * H
+    r_c = 4.5 * r_s
+    ref_f = o_pp.pp_accel(pos, m, 1.0, r_s, r_c, eps, 1.0) * m
+    ref_v = adjoint.pp_vjp(pos, m, 1.0, r_s, r_c, eps, lam)
+    with plan(GRID, n, precision, softening=eps, adjoint=True) as P:
+        F = host(P.pp_force(dev(pos), dev(m)))
+        g = host(P.pp_force_vjp(dev(pos), dev(m), dev(lam)))
+    assert np.all(np.isfinite(F)) and np.all(np.isfinite(g))
+    assert _err(F, ref_f) <= (1e-12 if precision == "fp64" else 1e-5)
+    assert _err(g, ref_v) <= tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_force_vjp_uniform_mass_and_invariants(case, precision):
     """Scalar mass (the per-pair mass factor folded out), and conservation:
