@@ -20,6 +20,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kScanItems = 8;                       // per thread
 constexpr int kScanTile = kThreads * kScanItems;    // per block
+static_assert(kScanItems == 8, "k_scan_tiles moves a thread's values as two int4");
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -107,24 +108,46 @@ k_scan_tiles(int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t len,
              int32_t* __restrict__ tile_sum) {
   __shared__ int wsum[kThreads / 64];
   int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  // a thread's kScanItems values are 32-byte aligned (in and out are device
+  // allocations): whole slices move as two int4, the ragged end one by one
+  const bool whole = base + kScanItems <= len;
   int v[kScanItems];
+  if (whole) {
+    const int4 a = reinterpret_cast<const int4*>(in + base)[0];
+    const int4 b = reinterpret_cast<const int4*>(in + base)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    if (ZERO) {
+      reinterpret_cast<int4*>(in + base)[0] = int4{0, 0, 0, 0};
+      reinterpret_cast<int4*>(in + base)[1] = int4{0, 0, 0, 0};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < len) ? in[base + k] : 0;
+    if (ZERO) {
+#pragma unroll
+      for (int k = 0; k < kScanItems; ++k)
+        if (base + k < len) in[base + k] = 0;
+    }
+  }
   int local = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < len) ? in[base + k] : 0;
-    local += v[k];
-  }
-  if (ZERO) {
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-      if (base + k < len) in[base + k] = 0;
-  }
+  for (int k = 0; k < kScanItems; ++k) local += v[k];
   int total;
   int run = block_exclusive(local, wsum, total);
+  int e[kScanItems];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < len) out[base + k] = run;
+    e[k] = run;
     run += v[k];
+  }
+  if (whole) {
+    reinterpret_cast<int4*>(out + base)[0] = int4{e[0], e[1], e[2], e[3]};
+    reinterpret_cast<int4*>(out + base)[1] = int4{e[4], e[5], e[6], e[7]};
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < len) out[base + k] = e[k];
   }
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
 }
@@ -146,10 +169,21 @@ k_scan_sums(int32_t* __restrict__ sums, int nt, int32_t* __restrict__ grand) {
   if (threadIdx.x == 0) *grand = carry;
 }
 
+// Whole tiles as int4 (consecutive threads, consecutive 16 bytes), the
+// ragged last tile one value at a time.
 __global__ void __launch_bounds__(kThreads)
 k_scan_add(int32_t* __restrict__ out, int64_t len, const int32_t* __restrict__ tile_off) {
   int64_t base = (int64_t)blockIdx.x * kScanTile;
   int add = tile_off[blockIdx.x];
+  if (base + kScanTile <= len) {
+    int4* o = reinterpret_cast<int4*>(out + base);
+    for (int k = threadIdx.x; k < kScanTile / 4; k += kThreads) {
+      int4 q = o[k];
+      q.x += add; q.y += add; q.z += add; q.w += add;
+      o[k] = q;
+    }
+    return;
+  }
   for (int k = threadIdx.x; k < kScanTile; k += kThreads) {
     int64_t i = base + k;
     if (i < len) out[i] += add;
@@ -217,9 +251,11 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 
 // out[0..len) = exclusive scan of in[0..len); out[len] = total; with
 // zero_in, in[0..len) is cleared as it is read. tmp needs scan_tmp_size(len)
-// entries.
+// entries; in and out must be 16-byte aligned (device allocations are).
 hipError_t launch_scan(int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hipStream_t s,
                        bool zero_in) {
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15)
+    return hipErrorInvalidValue;
   int nt = (int)((len + kScanTile - 1) / kScanTile);
   if (nt == 0) return launch_fill_i32(out, 1, 0, s);
   if (zero_in)
