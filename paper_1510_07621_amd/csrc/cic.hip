@@ -1,18 +1,20 @@
 // Cloud-in-cell mass deposit and the fused finite-difference gradient +
 // cloud-in-cell interpolation of the long-range (PM) force.
 //
-// Both kernels work on bricks of kBrick^3 grid cells. A particle in cell c
+// Both kernels work on bricks of grid cells. A particle in cell c
 // (offset t = (x - c h)/h in [0,1) per axis) touches the nodes c and c + 1 of
 // each axis with weights 1 - t and t (nodes at c h, periodic), so a brick's
-// particles touch (kBrick + 1)^3 nodes.
+// particles touch one node more per axis than it has cells.
 //
 // Deposit: each brick's 8^3 nodes gather the particles of the cells around
 // them (no atomics; see k_deposit_gather). The density is rho = sum m W / h^3.
 //
-// Interpolation: the brick's potential plus a two-node halo, (kBrick + 5)^3
-// values, is staged in LDS; the central-difference gradient (order 4:
+// Interpolation (bricks of BX x BX x BZ cells: 8^3, or 4 x 4 x 32 for the
+// FP32 path on grids of 32 cells and more): the brick's potential plus a
+// two-node halo, (BX + 5)^2 (BZ + 5) values, is staged in LDS; the
+// central-difference gradient (order 4:
 // [8(phi(c+1) - phi(c-1)) - (phi(c+2) - phi(c-2))] / 12h, or order 2) is formed
-// on the (kBrick + 1)^3 nodes in LDS, and each particle takes
+// on the (BX + 1)^2 (BZ + 1) nodes in LDS, and each particle takes
 // a = -sum_nodes W * grad. The result goes to the sorted-order PM buffer (to be
 // combined with the pair sum) or, for the PM-only call, straight to the
 // force array in input order as m * a.
@@ -85,40 +87,90 @@ k_deposit_gather(const typename Vec<T>::v4* __restrict__ rec,
   }
 }
 
-template <typename T>
+// Interpolation bricks of BX x BX x BZ cells: BX^2 z-runs of BZ cells each.
+// A deeper brick along z makes a wave's particles longer runs of consecutive
+// cells, so that for inputs stored in cell-like order (a lattice) the force
+// stores in input order fill whole cache lines.
+template <int BX, int BZ>
+struct InterpRuns {
+  static constexpr int kR = BX * BX;
+  int lo[kR];
+  int pre[kR + 1];
+};
+
+template <int BX, int BZ>
+__device__ inline void load_interp_runs(InterpRuns<BX, BZ>& R, const int32_t* __restrict__ start,
+                                        int lg, int bx0, int by0, int bz0) {
+  constexpr int kR = InterpRuns<BX, BZ>::kR;
+  static_assert(kR <= 64, "one wave scans the run counts");
+  const int t = threadIdx.x;
+  if (t < kR) {
+    int cx = bx0 + t / BX, cy = by0 + t % BX;
+    int c0 = (((cx << lg) | cy) << lg) | bz0;
+    int lo = start[c0];
+    R.lo[t] = lo;
+    R.pre[t + 1] = start[c0 + BZ] - lo;           // c0 + BZ <= ng^3: start has ng^3 + 1
+  }
+  __syncthreads();
+  if (t < 64) {
+    int v = (t < kR) ? R.pre[t + 1] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int u = __shfl_up(v, o, 64);
+      if (t >= o) v += u;
+    }
+    if (t < kR) R.pre[t + 1] = v;
+    if (t == 0) R.pre[0] = 0;
+  }
+  __syncthreads();
+}
+
+template <int BX, int BZ>
+__device__ __forceinline__ int find_interp_run(const InterpRuns<BX, BZ>& R, int f) {
+  int lo = 0, hi = InterpRuns<BX, BZ>::kR;        // invariant: pre[lo] <= f < pre[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (R.pre[mid] <= f) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, int BX, int BZ>
 __global__ void __launch_bounds__(kThreads)
 k_interp(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict__ skey,
          const int32_t* __restrict__ start, int ng, int lg, T inv_h, const T* __restrict__ phi,
          T c1, T c2, typename Vec<T>::v4* __restrict__ acc_out, const int32_t* __restrict__ perm,
          int64_t n, void* __restrict__ force, int force_fp32,
          const typename Vec<T>::v4* __restrict__ acc_pp) {
-  __shared__ T ph[kN5 * kN5 * kN5];
-  __shared__ T gr[3][kN1 * kN1 * kN1];
-  __shared__ BrickRuns R;
-  const int lb = lg - 3, mb = (1 << lb) - 1, mask = ng - 1;
+  constexpr int X1 = BX + 1, Z1 = BZ + 1;        // nodes touched per axis
+  constexpr int X5 = BX + 5, Z5 = BZ + 5;        // with the two-node gradient halo
+  __shared__ T ph[X5 * X5 * Z5];
+  __shared__ T gr[3][X1 * X1 * Z1];
+  __shared__ InterpRuns<BX, BZ> R;
+  const int mask = ng - 1, nbz = ng / BZ, nbx = ng / BX;
   const int b = blockIdx.x;
-  const int bz0 = (b & mb) * kBrick, by0 = ((b >> lb) & mb) * kBrick, bx0 = (b >> (2 * lb)) * kBrick;
-  for (int i = threadIdx.x; i < kN5 * kN5 * kN5; i += kThreads) {
-    int nx = i / (kN5 * kN5), ny = (i / kN5) % kN5, nz = i % kN5;
+  const int bz0 = (b % nbz) * BZ, by0 = ((b / nbz) % nbx) * BX, bx0 = (b / (nbz * nbx)) * BX;
+  for (int i = threadIdx.x; i < X5 * X5 * Z5; i += kThreads) {
+    int nx = i / (X5 * Z5), ny = (i / Z5) % X5, nz = i % Z5;
     int gx = (bx0 - 2 + nx) & mask, gy = (by0 - 2 + ny) & mask, gz = (bz0 - 2 + nz) & mask;
     ph[i] = phi[(((int64_t)gx << lg | gy) << lg) | gz];
   }
-  load_runs(R, start, lg, bx0, by0, bz0);       // contains __syncthreads
-  for (int i = threadIdx.x; i < kN1 * kN1 * kN1; i += kThreads) {
-    int nx = i / (kN1 * kN1), ny = (i / kN1) % kN1, nz = i % kN1;
-    int q = ((nx + 2) * kN5 + (ny + 2)) * kN5 + (nz + 2);
-    const int sx = kN5 * kN5, sy = kN5, sz = 1;
+  load_interp_runs(R, start, lg, bx0, by0, bz0);  // contains __syncthreads
+  for (int i = threadIdx.x; i < X1 * X1 * Z1; i += kThreads) {
+    int nx = i / (X1 * Z1), ny = (i / Z1) % X1, nz = i % Z1;
+    int q = ((nx + 2) * X5 + (ny + 2)) * Z5 + (nz + 2);
+    const int sx = X5 * Z5, sy = Z5, sz = 1;
     gr[0][i] = c1 * (ph[q + sx] - ph[q - sx]) + c2 * (ph[q + 2 * sx] - ph[q - 2 * sx]);
     gr[1][i] = c1 * (ph[q + sy] - ph[q - sy]) + c2 * (ph[q + 2 * sy] - ph[q - 2 * sy]);
     gr[2][i] = c1 * (ph[q + sz] - ph[q - sz]) + c2 * (ph[q + 2 * sz] - ph[q - 2 * sz]);
   }
   __syncthreads();
-  const int total = R.pre[kRows];
+  const int total = R.pre[InterpRuns<BX, BZ>::kR];
   for (int f = threadIdx.x; f < total; f += kThreads) {
-    int r = find_run(R, f);
+    int r = find_interp_run(R, f);
     int s = R.lo[r] + (f - R.pre[r]);
     typename Vec<T>::v4 p = rec[s];
-    int lx = r / kBrick, ly = r % kBrick, lz = (skey[s] & mask) - bz0;
+    int lx = r / BX, ly = r % BX, lz = (skey[s] & mask) - bz0;
     T tx = p.x * inv_h, ty = p.y * inv_h, tz = p.z * inv_h;
     T wx[2] = {T(1) - tx, tx}, wy[2] = {T(1) - ty, ty}, wz[2] = {T(1) - tz, tz};
     T ax = 0, ay = 0, az = 0;
@@ -129,7 +181,7 @@ k_interp(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict_
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
           T w = wx[a] * wy[c] * wz[d];
-          int q = ((lx + a) * kN1 + (ly + c)) * kN1 + (lz + d);
+          int q = ((lx + a) * X1 + (ly + c)) * Z1 + (lz + d);
           ax += w * gr[0][q];
           ay += w * gr[1][q];
           az += w * gr[2][q];
@@ -200,11 +252,22 @@ hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32
     c2 = T(-1.0 / (12.0 * h));
   }
   typename Vec<T>::v4* acc = force_out ? nullptr : (typename Vec<T>::v4*)W.acc_pm;
-  k_interp<T><<<nb, kThreads, 0, P->stream>>>((const typename Vec<T>::v4*)W.rec, W.skey,
-                                              W.start, P->ng, P->lg, T(1.0 / h),
-                                              (const T*)W.grid, c1, c2, acc, W.perm, n,
-                                              force_out, force_fp32,
-                                              (const typename Vec<T>::v4*)acc_pp);
+  // FP32 on grids of at least 32 cells: 4 x 4 x 32-cell bricks (as many as
+  // 8^3 ones, nb of them); FP64 keeps 8^3 (the deeper brick's LDS would cost
+  // it occupancy)
+  if constexpr (sizeof(T) == 4) {
+    if (P->ng >= 32) {
+      k_interp<T, 4, 32><<<nb, kThreads, 0, P->stream>>>(
+          (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / h),
+          (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
+          (const typename Vec<T>::v4*)acc_pp);
+      return hipGetLastError();
+    }
+  }
+  k_interp<T, kBrick, kBrick><<<nb, kThreads, 0, P->stream>>>(
+      (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / h),
+      (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
+      (const typename Vec<T>::v4*)acc_pp);
   return hipGetLastError();
 }
 
