@@ -9,10 +9,9 @@
 // Deposit: each brick's 8^3 nodes gather the particles of the cells around
 // them (no atomics; see k_deposit_gather). The density is rho = sum m W / h^3.
 //
-// Interpolation (bricks of BX x BX x BZ cells: 8^3, or 4 x 4 x 32 for the
-// FP32 path on grids of 32 cells and more): the brick's potential plus a
-// two-node halo, (BX + 5)^2 (BZ + 5) values, is staged in LDS; the
-// central-difference gradient (order 4:
+// Interpolation (bricks of BX x BX x BZ cells, 4 x 4 x 16): the brick's
+// potential plus a two-node halo, (BX + 5)^2 (BZ + 5) values, is staged in
+// LDS; the central-difference gradient (order 4:
 // [8(phi(c+1) - phi(c-1)) - (phi(c+2) - phi(c-2))] / 12h, or order 2) is formed
 // on the (BX + 1)^2 (BZ + 1) nodes in LDS, and each particle takes
 // a = -sum_nodes W * grad. The result goes to the sorted-order PM buffer (to be
@@ -237,11 +236,24 @@ hipError_t launch_deposit3(p3m_plan* P, const void* lam, void* grids) {
   return hipGetLastError();
 }
 
+// One interpolation launch over bricks of BX x BX x BZ cells (one workgroup
+// per brick); the grid's edge must be a multiple of BX and BZ.
+template <typename T, int BX, int BZ>
+hipError_t launch_interp_bricks(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
+                                const void* acc_pp, T c1, T c2) {
+  Workspace& W = P->ws;
+  const int nb = (int)(P->ncell / (BX * BX * BZ));
+  typename Vec<T>::v4* acc = force_out ? nullptr : (typename Vec<T>::v4*)W.acc_pm;
+  k_interp<T, BX, BZ><<<nb, kThreads, 0, P->stream>>>(
+      (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / P->h),
+      (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
+      (const typename Vec<T>::v4*)acc_pp);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
                          const void* acc_pp) {
-  Workspace& W = P->ws;
-  int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
   double h = P->h;
   T c1, c2;
   if (P->prm.fd_order == 2) {
@@ -251,24 +263,11 @@ hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32
     c1 = T(8.0 / (12.0 * h));
     c2 = T(-1.0 / (12.0 * h));
   }
-  typename Vec<T>::v4* acc = force_out ? nullptr : (typename Vec<T>::v4*)W.acc_pm;
-  // FP32 on grids of at least 32 cells: 4 x 4 x 32-cell bricks (as many as
-  // 8^3 ones, nb of them); FP64 keeps 8^3 (the deeper brick's LDS would cost
-  // it occupancy)
-  if constexpr (sizeof(T) == 4) {
-    if (P->ng >= 32) {
-      k_interp<T, 4, 32><<<nb, kThreads, 0, P->stream>>>(
-          (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / h),
-          (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
-          (const typename Vec<T>::v4*)acc_pp);
-      return hipGetLastError();
-    }
-  }
-  k_interp<T, kBrick, kBrick><<<nb, kThreads, 0, P->stream>>>(
-      (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / h),
-      (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
-      (const typename Vec<T>::v4*)acc_pp);
-  return hipGetLastError();
+  // Bricks of 4 x 4 x 16 cells (grids are at least 16 cells on a side): a
+  // wave's particles are 4 runs of 16 cells. Measured at 128^3 against 8^3
+  // bricks: FP32 65 -> 47 us (4 x 4 x 32: the same; 2 x 2 x 64: 55), FP64
+  // 77 -> 62 us (4 x 4 x 32: 72, its LDS costing occupancy; 2 x 2 x 32: 72).
+  return launch_interp_bricks<T, 4, 16>(P, n, force_out, force_fp32, acc_pp, c1, c2);
 }
 
 template hipError_t launch_deposit<float>(p3m_plan*);
