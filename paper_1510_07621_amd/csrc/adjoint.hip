@@ -65,8 +65,9 @@ k_divergence(const T* __restrict__ grids, int lg, T c1, T c2, T* __restrict__ ou
 
 // pos_bar_k / m_k = sum_c grad W(x_k - c) [h^-3 psi(c) - lam_k . (D phi)(c)],
 // to the sorted buffer (added by the pair adjoint) or, for the mesh-only
-// call, times m_k straight to pos_bar in input order.
-template <typename T>
+// call, times m_k straight to pos_bar in input order. Bricks of BX x BX x BZ
+// cells, as the forward interpolation.
+template <typename T, int BX, int BZ>
 __global__ void __launch_bounds__(kThreads)
 k_interp_vjp(const typename Vec<T>::v4* __restrict__ rec,
              const typename Vec<T>::v4* __restrict__ lam, const int32_t* __restrict__ skey,
@@ -75,40 +76,42 @@ k_interp_vjp(const typename Vec<T>::v4* __restrict__ rec,
              typename Vec<T>::v4* __restrict__ acc_out, const int32_t* __restrict__ perm,
              int64_t n, double* __restrict__ pos_bar,
              const typename Vec<T>::v4* __restrict__ acc_pp) {
-  __shared__ T ph[kN5 * kN5 * kN5];
-  __shared__ T gr[3][kN1 * kN1 * kN1];
-  __shared__ T ps[kN1 * kN1 * kN1];
-  __shared__ BrickRuns R;
-  const int lb = lg - 3, mb = (1 << lb) - 1, mask = ng - 1;
+  constexpr int X1 = BX + 1, Z1 = BZ + 1;        // nodes touched per axis
+  constexpr int X5 = BX + 5, Z5 = BZ + 5;        // with the two-node gradient halo
+  __shared__ T ph[X5 * X5 * Z5];
+  __shared__ T gr[3][X1 * X1 * Z1];
+  __shared__ T ps[X1 * X1 * Z1];
+  __shared__ InterpRuns<BX, BZ> R;
+  const int mask = ng - 1, nbz = ng / BZ, nbx = ng / BX;
   const int b = blockIdx.x;
-  const int bz0 = (b & mb) * kBrick, by0 = ((b >> lb) & mb) * kBrick, bx0 = (b >> (2 * lb)) * kBrick;
-  for (int i = threadIdx.x; i < kN5 * kN5 * kN5; i += kThreads) {
-    int nx = i / (kN5 * kN5), ny = (i / kN5) % kN5, nz = i % kN5;
+  const int bz0 = (b % nbz) * BZ, by0 = ((b / nbz) % nbx) * BX, bx0 = (b / (nbz * nbx)) * BX;
+  for (int i = threadIdx.x; i < X5 * X5 * Z5; i += kThreads) {
+    int nx = i / (X5 * Z5), ny = (i / Z5) % X5, nz = i % Z5;
     int gx = (bx0 - 2 + nx) & mask, gy = (by0 - 2 + ny) & mask, gz = (bz0 - 2 + nz) & mask;
     ph[i] = phi[(((int64_t)gx << lg | gy) << lg) | gz];
   }
-  for (int i = threadIdx.x; i < kN1 * kN1 * kN1; i += kThreads) {
-    int nx = i / (kN1 * kN1), ny = (i / kN1) % kN1, nz = i % kN1;
+  for (int i = threadIdx.x; i < X1 * X1 * Z1; i += kThreads) {
+    int nx = i / (X1 * Z1), ny = (i / Z1) % X1, nz = i % Z1;
     int gx = (bx0 + nx) & mask, gy = (by0 + ny) & mask, gz = (bz0 + nz) & mask;
     ps[i] = inv_h3 * psi[(((int64_t)gx << lg | gy) << lg) | gz];
   }
-  load_runs(R, start, lg, bx0, by0, bz0);       // contains __syncthreads
-  for (int i = threadIdx.x; i < kN1 * kN1 * kN1; i += kThreads) {
-    int nx = i / (kN1 * kN1), ny = (i / kN1) % kN1, nz = i % kN1;
-    int q = ((nx + 2) * kN5 + (ny + 2)) * kN5 + (nz + 2);
-    const int sx = kN5 * kN5, sy = kN5, sz = 1;
+  load_interp_runs(R, start, lg, bx0, by0, bz0);  // contains __syncthreads
+  for (int i = threadIdx.x; i < X1 * X1 * Z1; i += kThreads) {
+    int nx = i / (X1 * Z1), ny = (i / Z1) % X1, nz = i % Z1;
+    int q = ((nx + 2) * X5 + (ny + 2)) * Z5 + (nz + 2);
+    const int sx = X5 * Z5, sy = Z5, sz = 1;
     gr[0][i] = c1 * (ph[q + sx] - ph[q - sx]) + c2 * (ph[q + 2 * sx] - ph[q - 2 * sx]);
     gr[1][i] = c1 * (ph[q + sy] - ph[q - sy]) + c2 * (ph[q + 2 * sy] - ph[q - 2 * sy]);
     gr[2][i] = c1 * (ph[q + sz] - ph[q - sz]) + c2 * (ph[q + 2 * sz] - ph[q - 2 * sz]);
   }
   __syncthreads();
-  const int total = R.pre[kRows];
+  const int total = R.pre[InterpRuns<BX, BZ>::kR];
   for (int f = threadIdx.x; f < total; f += kThreads) {
-    int r = find_run(R, f);
+    int r = find_interp_run(R, f);
     int s = R.lo[r] + (f - R.pre[r]);
     const typename Vec<T>::v4 p = rec[s];
     const typename Vec<T>::v4 l = lam[s];
-    int lx = r / kBrick, ly = r % kBrick, lz = (skey[s] & mask) - bz0;
+    int lx = r / BX, ly = r % BX, lz = (skey[s] & mask) - bz0;
     T tx = p.x * inv_h, ty = p.y * inv_h, tz = p.z * inv_h;
     T wx[2] = {T(1) - tx, tx}, wy[2] = {T(1) - ty, ty}, wz[2] = {T(1) - tz, tz};
     const T dw[2] = {-inv_h, inv_h};               // d/dx of (1 - t, t)
@@ -119,7 +122,7 @@ k_interp_vjp(const typename Vec<T>::v4* __restrict__ rec,
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-          const int q = ((lx + a) * kN1 + (ly + c)) * kN1 + (lz + d);
+          const int q = ((lx + a) * X1 + (ly + c)) * Z1 + (lz + d);
           const T sv = ps[q] - (l.x * gr[0][q] + l.y * gr[1][q] + l.z * gr[2][q]);
           bx += dw[a] * wy[c] * wz[d] * sv;
           by += wx[a] * dw[c] * wz[d] * sv;
@@ -198,12 +201,15 @@ hipError_t launch_deposit_lambda(p3m_plan* P) {
 template <typename T>
 hipError_t launch_interp_vjp(p3m_plan* P, int64_t n, double* pos_bar, const void* acc_pp) {
   Workspace& W = P->ws;
-  const int nb = (int)(P->ncell / (kBrick * kBrick * kBrick));
+  // bricks of 4 x 4 x 16 cells, as the forward interpolation (grids are at
+  // least 16 cells on a side)
+  constexpr int BX = 4, BZ = 16;
+  const int nb = (int)(P->ncell / (BX * BX * BZ));
   T c1, c2;
   fd_coefficients(P, c1, c2);
   const double h = P->h;
   typename Vec<T>::v4* acc = pos_bar ? nullptr : (typename Vec<T>::v4*)W.acc_pm;
-  k_interp_vjp<T><<<nb, kThreads, 0, P->stream>>>(
+  k_interp_vjp<T, BX, BZ><<<nb, kThreads, 0, P->stream>>>(
       (const typename Vec<T>::v4*)W.rec, (const typename Vec<T>::v4*)W.lam, W.skey, W.start,
       P->ng, P->lg, T(1.0 / h), T(1.0 / (h * h * h)), (const T*)W.grid, (const T*)W.grid2, c1,
       c2, acc, W.perm, n, pos_bar, (const typename Vec<T>::v4*)acc_pp);
