@@ -3,8 +3,9 @@
 ``force(plan, pos, mass)`` is the P3M force as a differentiable function of
 the positions; its backward is the library's force adjoint
 (``p3m_force_vjp``). ``leapfrog(plan, pos, mom, mass, dt, box, steps)`` runs
-``steps`` kick-drift-kick steps with the library's kick, drift and force
-calls and is differentiable in the initial positions and momenta; its
+``steps`` kick-drift-kick steps with the library's calls (the first half-kick
+and the drift fused into one pass, then the force and the second half-kick)
+and is differentiable in the initial positions and momenta; its
 backward runs the transposed steps with the force adjoint and the drift
 transpose, recomputing the trajectory segment by segment from stored
 checkpoints (every ``segment`` steps, default ceil(sqrt(steps)), so memory
@@ -59,8 +60,7 @@ def force(plan: "binding.Plan", pos: torch.Tensor, mass) -> torch.Tensor:
 def _steps(plan, x, p, F, mass, dt, box, k, keep=None):
     """k KDK steps in place on (x, p, F); appends a copy of each new x to keep."""
     for _ in range(k):
-        binding.kick(p, F, 0.5 * dt)
-        binding.drift(x, p, mass, dt, box)
+        binding.kick_drift(x, p, F, mass, 0.5 * dt, dt, box)   # = kick, then drift
         plan.force(x, mass, out=F)
         binding.kick(p, F, 0.5 * dt)
         if keep is not None:
