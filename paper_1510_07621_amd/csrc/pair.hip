@@ -407,7 +407,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   using T4 = typename Vec<T>::v4;
   constexpr int kCap = Stage<T, VJP>::kCap, kStage = Stage<T, VJP>::kPer;
   const int lane = threadIdx.x;
-  const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
+  const int ng = A.ng, mask = ng - 1, lgG = A.lgG, G = A.G, GG = G * G;
   // The force over the softened-distance table runs on positions scaled by
   // the table's s (the bin coordinate then needs no extra multiply). An i
   // and its own staged copy must come out bit-identical (the self pair's
