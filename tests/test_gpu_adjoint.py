@@ -97,6 +97,19 @@ def test_coincident_particles_contribute_nothing(precision, tol, soft_cells):
     assert _err(g, ref_v) <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+@pytest.mark.parametrize("fd_order,deconv_power", [(2, 2), (4, 0)])
+def test_pm_vjp_gradient_order_and_deconvolution(case, precision, tol, fd_order, deconv_power):
+    """The mesh adjoint with the plan's other options (2-point gradient, no
+    CIC deconvolution) against the oracle's transpose of the same force."""
+    pos, m, lam, _, _ = case
+    ref = adjoint.pm_vjp(pos, m, 1.0, GRID, 1.25 * H, lam, fd_order=fd_order,
+                         deconv_power=deconv_power)
+    with _vjp_plan(pos.shape[1], precision, fd_order=fd_order, deconv_power=deconv_power) as P:
+        got = host(P.pm_force_vjp(dev(pos), dev(m), dev(lam)))
+    assert _err(got, ref) <= tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_force_vjp_uniform_mass_and_invariants(case, precision):
     """Scalar mass (the per-pair mass factor folded out), and conservation:

@@ -175,6 +175,27 @@ def test_pm_force_parity(uniform32, precision, tol):
     assert e["rms"] <= tol, e
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+@pytest.mark.parametrize("fd_order,deconv_power", [(2, 2), (4, 0), (2, 0)])
+def test_pm_force_parity_gradient_order_and_deconvolution(precision, tol, fd_order,
+                                                          deconv_power):
+    """The plan's other mesh options, the 2-point gradient and the Green's
+    function without the CIC deconvolution, against the oracle's, in a box
+    of side 1.5 on a 32^3 grid with per-particle masses."""
+    grid, box, n = 32, 1.5, 6000
+    rng = np.random.default_rng(71)
+    pos = ics.uniform(n, box, seed=72)
+    m = rng.uniform(0.5, 1.5, n) / n
+    r_s = 1.25 * box / grid
+    ref = o_pm.pm_accel(pos, m, box, grid, r_s, 1.0, fd_order=fd_order,
+                        deconv_power=deconv_power) * m
+    with plan(grid, n, precision, box=box, fd_order=fd_order,
+              deconv_power=deconv_power) as P:
+        F = host(P.pm_force(dev(pos), dev(m)))
+    e = _err(F, ref)
+    assert e["rms"] <= tol, e
+
+
 @pytest.mark.parametrize("precision,tol,tight", [("fp64", 1e-6, 1e-10), ("fp32", 1e-3, 1e-4)])
 def test_p3m_force_parity(uniform32, precision, tol, tight):
     w, pos, a_pp, a_pm = uniform32
