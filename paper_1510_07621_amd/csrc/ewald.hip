@@ -22,7 +22,9 @@
 namespace p3m {
 namespace {
 
-constexpr int kEwThreads = 256;
+constexpr int kEwI = 64;                       // i-particles per block of the pair sum
+constexpr int kEwWaves = 8;                    // waves per block, each on a share of the j's
+constexpr int kEwThreads = kEwI * kEwWaves;
 
 // c(r) at one octant node, in FP64.
 __global__ void __launch_bounds__(256)
@@ -114,13 +116,19 @@ __device__ __forceinline__ double min_image(double d, double box, double inv_box
   return d - box * rint(d * inv_box);
 }
 
-// All pairs, j tiles in LDS; one i per thread.
+// All pairs, j tiles in LDS. A block holds kEwI i-particles, one per lane,
+// and kEwWaves waves that each take their own contiguous share of every j
+// tile, so a small n still spreads over every CU with several waves per SIMD
+// to cover the latency of the table's gathers. The waves' partial sums are
+// added in wave order at the end, so the result does not depend on timing.
 __global__ void __launch_bounds__(kEwThreads)
 k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
            double ms, double box, double eps2, double negG, const double4* __restrict__ tab,
            int E, void* __restrict__ force, int force_fp32) {
   __shared__ double4 tile[kEwThreads];
-  const int64_t i = (int64_t)blockIdx.x * kEwThreads + threadIdx.x;
+  __shared__ double red[3][kEwWaves][kEwI];
+  const int lane = threadIdx.x % kEwI, wave = threadIdx.x / kEwI;
+  const int64_t i = (int64_t)blockIdx.x * kEwI + lane;
   const bool live = i < n;
   const double xi = live ? pos[i] : 0.0, yi = live ? pos[n + i] : 0.0,
                zi = live ? pos[2 * n + i] : 0.0;
@@ -133,14 +141,17 @@ k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__
       tile[threadIdx.x] = make_double4(pos[jl], pos[n + jl], pos[2 * n + jl],
                                        mass ? mass[jl] : ms);
     __syncthreads();
-    const int cnt = (int)min<int64_t>(kEwThreads, n - j0);
+    // this wave's entries [tb, tb + cnt) of the tile (cnt <= 0 past the end)
+    const int tb = wave * kEwI;
+    const int64_t jb = j0 + tb;
+    const int cnt = (int)min<int64_t>(kEwI, n - jb);
     for (int t = 0; t < cnt; ++t) {
-      const double4 pj = tile[t];
+      const double4 pj = tile[tb + t];
       const double dx = min_image(xi - pj.x, box, inv_box);
       const double dy = min_image(yi - pj.y, box, inv_box);
       const double dz = min_image(zi - pj.z, box, inv_box);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      if (!live || j0 + t == i || r2 == 0.0) continue;
+      if (!live || jb + t == i || r2 == 0.0) continue;
       const double inv = rsqrt(r2 + eps2);
       const double w = inv * inv * inv;
       const double3 c = ewald_corr(tab, E, inv_h, dx, dy, dz);
@@ -149,7 +160,18 @@ k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__
       az += pj.w * (dz * w + c.z);
     }
   }
-  if (!live) return;
+  red[0][wave][lane] = ax;
+  red[1][wave][lane] = ay;
+  red[2][wave][lane] = az;
+  __syncthreads();
+  if (wave != 0 || !live) return;
+  ax = ay = az = 0;
+#pragma unroll
+  for (int w = 0; w < kEwWaves; ++w) {
+    ax += red[0][w][lane];
+    ay += red[1][w][lane];
+    az += red[2][w][lane];
+  }
   const double m = mass ? mass[i] : ms;
   const double fx = negG * m * ax, fy = negG * m * ay, fz = negG * m * az;
   if (force_fp32) {
@@ -192,7 +214,7 @@ hipError_t launch_ewald_table(p3m_plan* P) {
 
 hipError_t launch_pp_ewald(p3m_plan* P, int64_t n, const double* pos, const double* mass,
                            double ms, void* force, int force_fp32) {
-  const unsigned blocks = (unsigned)((n + kEwThreads - 1) / kEwThreads);
+  const unsigned blocks = (unsigned)((n + kEwI - 1) / kEwI);
   k_pp_ewald<<<blocks, kEwThreads, 0, P->stream>>>(
       n, pos, mass, ms, P->prm.box, P->eps * P->eps, -P->prm.G,
       (const double4*)P->ws.ewald_tab, P->prm.ewald_gridsize, force, force_fp32);
