@@ -197,7 +197,9 @@ int p3m_power_spectrum(p3m_plan* plan, int64_t n, const double* pos, const doubl
  * ewald_gridsize^3 node grid (spacing box / ewald_gridsize; c is odd in each
  * coordinate, so the octant [0, box/2]^3 is stored) and interpolated
  * trilinearly. Softening acts on the minimum-image term only. Arguments as
- * for p3m_force; the plan must have ewald_gridsize > 0 (else EINVAL). */
+ * for p3m_force; the plan must have ewald_gridsize > 0 (else EINVAL). The
+ * call bins the particles into the plan's cells first, as the force calls
+ * do, and sums over the i's in cell order. */
 int pp_ewald_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
                    double mass_scalar, void* force, int32_t force_fp32);
 

@@ -121,15 +121,21 @@ __device__ __forceinline__ double min_image(double d, double box, double inv_box
 // tile, so a small n still spreads over every CU with several waves per SIMD
 // to cover the latency of the table's gathers. The waves' partial sums are
 // added in wave order at the end, so the result does not depend on timing.
+// The i-particles are taken in cell order (order[s] is the input index of
+// sorted slot s), so a block's i's sit in a few neighbouring cells and, for
+// one broadcast j, its lanes' separations fall on nearby table nodes that
+// share cache lines.
 __global__ void __launch_bounds__(kEwThreads)
 k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
            double ms, double box, double eps2, double negG, const double4* __restrict__ tab,
-           int E, void* __restrict__ force, int force_fp32) {
+           int E, const int32_t* __restrict__ order, void* __restrict__ force,
+           int force_fp32) {
   __shared__ double4 tile[kEwThreads];
   __shared__ double red[3][kEwWaves][kEwI];
   const int lane = threadIdx.x % kEwI, wave = threadIdx.x / kEwI;
-  const int64_t i = (int64_t)blockIdx.x * kEwI + lane;
-  const bool live = i < n;
+  const int64_t slot = (int64_t)blockIdx.x * kEwI + lane;
+  const bool live = slot < n;
+  const int64_t i = live ? (int64_t)order[slot] : -1;
   const double xi = live ? pos[i] : 0.0, yi = live ? pos[n + i] : 0.0,
                zi = live ? pos[2 * n + i] : 0.0;
   const double inv_box = 1.0 / box, inv_h = E / box;
@@ -213,11 +219,11 @@ hipError_t launch_ewald_table(p3m_plan* P) {
 }
 
 hipError_t launch_pp_ewald(p3m_plan* P, int64_t n, const double* pos, const double* mass,
-                           double ms, void* force, int force_fp32) {
+                           double ms, const int32_t* order, void* force, int force_fp32) {
   const unsigned blocks = (unsigned)((n + kEwI - 1) / kEwI);
   k_pp_ewald<<<blocks, kEwThreads, 0, P->stream>>>(
       n, pos, mass, ms, P->prm.box, P->eps * P->eps, -P->prm.G,
-      (const double4*)P->ws.ewald_tab, P->prm.ewald_gridsize, force, force_fp32);
+      (const double4*)P->ws.ewald_tab, P->prm.ewald_gridsize, order, force, force_fp32);
   return hipGetLastError();
 }
 

@@ -749,7 +749,11 @@ int pp_ewald_force(p3m_plan* P, int64_t n, const double* pos, const double* mass
       overlaps(force, fbytes, mass, (size_t)n * sizeof(double)))
     return P3M_EINVAL;
   P->timing_slot = -1;
-  return status_of(launch_pp_ewald(P, n, pos, mass, mass_scalar, force, force_fp32 ? 1 : 0));
+  // the binning's permutation orders the i-particles by cell (table locality)
+  hipError_t e = launch_bin(P, n, pos, mass, mass_scalar);
+  if (e != hipSuccess) return status_of(e);
+  return status_of(launch_pp_ewald(P, n, pos, mass, mass_scalar, P->ws.perm, force,
+                                   force_fp32 ? 1 : 0));
 }
 
 int p3m_ewald_correction(p3m_plan* P, int64_t npts, const double* r, double* c_out) {

@@ -130,7 +130,7 @@ hipError_t launch_tables(p3m_plan* P);
 
 hipError_t launch_ewald_table(p3m_plan* P);
 hipError_t launch_pp_ewald(p3m_plan* P, int64_t n, const double* pos, const double* mass,
-                           double ms, void* force, int force_fp32);
+                           double ms, const int32_t* order, void* force, int force_fp32);
 hipError_t launch_ewald_eval(p3m_plan* P, int64_t npts, const double* r, double* out);
 template <typename T>
 hipError_t launch_power_spectrum(p3m_plan* P, int nbins, double r_tophat, double* k_out,

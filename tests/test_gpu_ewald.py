@@ -76,6 +76,27 @@ def test_pp_ewald_force_on_node_separations_is_exact():
     assert metrics.force_errors(F, ref)["rms"] <= 1e-10
 
 
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 600])
+def test_pp_ewald_force_ragged_sizes(n):
+    """Sizes below one block of 64 i-particles, one past it, and a last j tile
+    of 88 entries (600 = 512 + 88), where six of the eight waves of a block
+    have no entries: node-lattice sites as above, so the force equals O-EW to
+    rounding. A lone particle feels nothing: its periodic images and the
+    neutralising background balance by symmetry, and it has no pairs."""
+    E, box = 32, 1.0
+    rng = np.random.default_rng(86 + n)
+    sites = rng.choice(E ** 3, size=n, replace=False)
+    pos = np.stack(np.unravel_index(sites, (E, E, E))).astype(np.float64) * (box / E)
+    m = rng.uniform(0.5, 1.5, n) / n
+    with plan(16, n, "fp64", ewald_gridsize=E) as P:
+        F = host(P.pp_ewald_force(dev(pos), dev(m)))
+    if n == 1:
+        assert np.all(F == 0.0)
+        return
+    ref = ewald.ewald_force(pos, m, box, G=1.0)
+    assert metrics.force_errors(F, ref)["rms"] <= 1e-10
+
+
 def test_pp_ewald_force_uniform32():
     """The 32^3 uniform workload with its softening (0.03 mean spacing):
     pp_ewald_force with a 64^3 table against O-EW on 256 sampled particles."""
