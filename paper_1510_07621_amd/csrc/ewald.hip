@@ -83,8 +83,26 @@ k_ewald_table(int E, double box, double4* __restrict__ tab) {
   tab[idx] = make_double4(cx, cy, cz, 0.0);
 }
 
-// Trilinear c(r) from the octant table, r a minimum-image separation.
-__device__ __forceinline__ double3 ewald_corr(const double4* __restrict__ tab, int E,
+// The node table regrouped for the interpolation: entry (i, j, k), k < E/2,
+// holds c at nodes (i, j, k) and (i, j, k + 1) as three double2 (48 bytes,
+// 16-byte aligned), so the two z-corners of a trilinear cell come in three
+// aligned 16-byte loads instead of the four that two padded double4 nodes
+// take.
+__global__ void __launch_bounds__(256)
+k_ewald_zpairs(int E, const double4* __restrict__ tab, double2* __restrict__ zp) {
+  const int H = E / 2 + 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= H * H * (H - 1)) return;
+  const int col = idx / (H - 1), k = idx % (H - 1);
+  const double4 a = tab[col * H + k], b = tab[col * H + k + 1];
+  zp[3 * idx + 0] = make_double2(a.x, a.y);
+  zp[3 * idx + 1] = make_double2(a.z, b.x);
+  zp[3 * idx + 2] = make_double2(b.y, b.z);
+}
+
+// Trilinear c(r) from the octant table (z-pair layout), r a minimum-image
+// separation.
+__device__ __forceinline__ double3 ewald_corr(const double2* __restrict__ zp, int E,
                                               double inv_h, double dx, double dy, double dz) {
   const int H = E / 2 + 1;
   // clamped to the octant (also keeps a non-finite input inside the table)
@@ -97,15 +115,15 @@ __device__ __forceinline__ double3 ewald_corr(const double4* __restrict__ tab, i
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const double w = (a ? tx : 1.0 - tx) * (b ? ty : 1.0 - ty) * (d ? tz : 1.0 - tz);
-        const double4 v = tab[((ix + a) * H + (iy + b)) * H + (iz + d)];
-        c.x += w * v.x;
-        c.y += w * v.y;
-        c.z += w * v.z;
-      }
+    for (int b = 0; b < 2; ++b) {
+      const double wxy = (a ? tx : 1.0 - tx) * (b ? ty : 1.0 - ty);
+      const double2* e = zp + 3 * (((ix + a) * H + (iy + b)) * (H - 1) + iz);
+      const double2 v0 = e[0], v1 = e[1], v2 = e[2];
+      const double w0 = wxy * (1.0 - tz), w1 = wxy * tz;
+      c.x += w0 * v0.x + w1 * v1.y;
+      c.y += w0 * v0.y + w1 * v2.x;
+      c.z += w0 * v1.x + w1 * v2.y;
+    }
   c.x = dx < 0 ? -c.x : c.x;
   c.y = dy < 0 ? -c.y : c.y;
   c.z = dz < 0 ? -c.z : c.z;
@@ -127,7 +145,7 @@ __device__ __forceinline__ double min_image(double d, double box, double inv_box
 // share cache lines.
 __global__ void __launch_bounds__(kEwThreads)
 k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
-           double ms, double box, double eps2, double negG, const double4* __restrict__ tab,
+           double ms, double box, double eps2, double negG, const double2* __restrict__ tab,
            int E, const int32_t* __restrict__ order, void* __restrict__ force,
            int force_fp32) {
   __shared__ double4 tile[kEwThreads];
@@ -196,7 +214,7 @@ k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__
 // The interpolated correction at given minimum-image separations.
 __global__ void __launch_bounds__(256)
 k_ewald_eval(int64_t npts, const double* __restrict__ r, double box,
-             const double4* __restrict__ tab, int E, double* __restrict__ out) {
+             const double2* __restrict__ tab, int E, double* __restrict__ out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npts) return;
   const double inv_box = 1.0 / box;
@@ -215,6 +233,11 @@ hipError_t launch_ewald_table(p3m_plan* P) {
   const int total = H * H * H;
   k_ewald_table<<<(total + 255) / 256, 256, 0, P->stream>>>(E, P->prm.box,
                                                            (double4*)P->ws.ewald_tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int pairs = H * H * (H - 1);
+  k_ewald_zpairs<<<(pairs + 255) / 256, 256, 0, P->stream>>>(
+      E, (const double4*)P->ws.ewald_tab, (double2*)P->ws.ewald_zpair);
   return hipGetLastError();
 }
 
@@ -223,13 +246,13 @@ hipError_t launch_pp_ewald(p3m_plan* P, int64_t n, const double* pos, const doub
   const unsigned blocks = (unsigned)((n + kEwI - 1) / kEwI);
   k_pp_ewald<<<blocks, kEwThreads, 0, P->stream>>>(
       n, pos, mass, ms, P->prm.box, P->eps * P->eps, -P->prm.G,
-      (const double4*)P->ws.ewald_tab, P->prm.ewald_gridsize, order, force, force_fp32);
+      (const double2*)P->ws.ewald_zpair, P->prm.ewald_gridsize, order, force, force_fp32);
   return hipGetLastError();
 }
 
 hipError_t launch_ewald_eval(p3m_plan* P, int64_t npts, const double* r, double* out) {
   k_ewald_eval<<<(unsigned)((npts + 255) / 256), 256, 0, P->stream>>>(
-      npts, r, P->prm.box, (const double4*)P->ws.ewald_tab, P->prm.ewald_gridsize, out);
+      npts, r, P->prm.box, (const double2*)P->ws.ewald_zpair, P->prm.ewald_gridsize, out);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ void free_workspace(p3m_plan* P) {
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
                   W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.split_tab64, W.lam,
-                  W.grid2, W.lam_grid, W.power_acc, W.ewald_tab};
+                  W.grid2, W.lam_grid, W.power_acc, W.ewald_tab, W.ewald_zpair};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -614,6 +614,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
   if (q.ewald_gridsize) {
     const int64_t H = q.ewald_gridsize / 2 + 1;
     W.ewald_tab = dev_alloc<double4>(H * H * H, err);
+    W.ewald_zpair = dev_alloc<double2>(H * H * (H - 1) * 3, err);
   }
   if (q.adjoint) {
     W.lam = dev_alloc<unsigned char>(nn * 4 * real, err);

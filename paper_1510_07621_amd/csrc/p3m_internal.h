@@ -56,6 +56,7 @@ struct Workspace {
   double* split_tab64 = nullptr;  // [kSplitCoef64][kSplitBins + 1] FP64 pieces of f(r)
   double* power_acc = nullptr;  // [3 * kMaxPowerBins + 2] power-spectrum sums
   void* ewald_tab = nullptr;    // [(E/2+1)^3] double4 Ewald correction octant (E > 0)
+  void* ewald_zpair = nullptr;  // [(E/2+1)^2 (E/2)][3] double2: z-adjacent node pairs of it
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
   void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
