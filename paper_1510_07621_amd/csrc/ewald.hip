@@ -139,10 +139,11 @@ __device__ __forceinline__ double min_image(double d, double box, double inv_box
 // tile, so a small n still spreads over every CU with several waves per SIMD
 // to cover the latency of the table's gathers. The waves' partial sums are
 // added in wave order at the end, so the result does not depend on timing.
-// The i-particles are taken in cell order (order[s] is the input index of
-// sorted slot s), so a block's i's sit in a few neighbouring cells and, for
-// one broadcast j, its lanes' separations fall on nearby table nodes that
-// share cache lines.
+// The i- and j-particles are both taken in cell order (order[s] is the input
+// index of sorted slot s): a block's i's sit in a few neighbouring cells, so
+// for one broadcast j its lanes' separations fall on nearby table nodes that
+// share cache lines, and consecutive j's are neighbours, so consecutive
+// steps revisit those lines.
 __global__ void __launch_bounds__(kEwThreads)
 k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
            double ms, double box, double eps2, double negG, const double2* __restrict__ tab,
@@ -161,9 +162,10 @@ k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__
   for (int64_t j0 = 0; j0 < n; j0 += kEwThreads) {
     const int64_t jl = j0 + threadIdx.x;
     __syncthreads();
-    if (jl < n)
-      tile[threadIdx.x] = make_double4(pos[jl], pos[n + jl], pos[2 * n + jl],
-                                       mass ? mass[jl] : ms);
+    if (jl < n) {
+      const int64_t j = order[jl];
+      tile[threadIdx.x] = make_double4(pos[j], pos[n + j], pos[2 * n + j], mass ? mass[j] : ms);
+    }
     __syncthreads();
     // this wave's entries [tb, tb + cnt) of the tile (cnt <= 0 past the end)
     const int tb = wave * kEwI;
@@ -175,7 +177,7 @@ k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__
       const double dy = min_image(yi - pj.y, box, inv_box);
       const double dz = min_image(zi - pj.z, box, inv_box);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      if (!live || jb + t == i || r2 == 0.0) continue;
+      if (!live || jb + t == slot || r2 == 0.0) continue;
       const double inv = rsqrt(r2 + eps2);
       const double w = inv * inv * inv;
       const double3 c = ewald_corr(tab, E, inv_h, dx, dy, dz);
