@@ -138,7 +138,10 @@ __device__ __forceinline__ double min_image(double d, double box, double inv_box
 // and kEwWaves waves that each take their own contiguous share of every j
 // tile, so a small n still spreads over every CU with several waves per SIMD
 // to cover the latency of the table's gathers. The waves' partial sums are
-// added in wave order at the end, so the result does not depend on timing.
+// added in wave order at the end (no atomics), so the summation order is
+// that of the particles in the sorted order below. Within a cell that order
+// is the binning's atomic rank, which may differ between calls: the result
+// can change at rounding level from call to call, like the P3M force.
 // The i- and j-particles are both taken in cell order (order[s] is the input
 // index of sorted slot s): a block's i's sit in a few neighbouring cells, so
 // for one broadcast j its lanes' separations fall on nearby table nodes that
