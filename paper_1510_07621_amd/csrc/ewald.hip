@@ -137,16 +137,15 @@ __device__ __forceinline__ double min_image(double d, double box, double inv_box
 // All pairs, j tiles in LDS. A block holds kEwI i-particles, one per lane,
 // and kEwWaves waves that each take their own contiguous share of every j
 // tile, so a small n still spreads over every CU with several waves per SIMD
-// to cover the latency of the table's gathers. The waves' partial sums are
-// added in wave order at the end (no atomics), so the summation order is
-// that of the particles in the sorted order below. Within a cell that order
-// is the binning's atomic rank, which may differ between calls: the result
-// can change at rounding level from call to call, like the P3M force.
-// The i- and j-particles are both taken in cell order (order[s] is the input
-// index of sorted slot s): a block's i's sit in a few neighbouring cells, so
-// for one broadcast j its lanes' separations fall on nearby table nodes that
-// share cache lines, and consecutive j's are neighbours, so consecutive
-// steps revisit those lines.
+// to cover the latency of the table's gathers. The i- and j-particles are
+// both taken in cell order (order[s] is the input index of sorted slot s): a
+// block's i's sit in a few neighbouring cells, so for one broadcast j its
+// lanes' separations fall on nearby table nodes that share cache lines, and
+// consecutive j's are neighbours, so consecutive steps revisit those lines.
+// The waves' partial sums are added in wave order at the end (no atomics),
+// so the summation order is the sorted order. Within a cell that order is
+// the binning's atomic rank, which may differ between calls: the result can
+// change at rounding level from call to call, like the P3M force.
 __global__ void __launch_bounds__(kEwThreads)
 k_pp_ewald(int64_t n, const double* __restrict__ pos, const double* __restrict__ mass,
            double ms, double box, double eps2, double negG, const double2* __restrict__ tab,
