@@ -23,7 +23,7 @@ namespace p3m {
 namespace {
 
 constexpr int kEwI = 64;                       // i-particles per block of the pair sum
-constexpr int kEwWaves = 8;                    // waves per block, each on a share of the j's
+constexpr int kEwWaves = 16;                   // waves per block, each on a share of the j's
 constexpr int kEwThreads = kEwI * kEwWaves;
 
 // c(r) at one octant node, in FP64.

@@ -78,9 +78,9 @@ def test_pp_ewald_force_on_node_separations_is_exact():
 
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 600])
 def test_pp_ewald_force_ragged_sizes(n):
-    """Sizes below one block of 64 i-particles, one past it, and a last j tile
-    of 88 entries (600 = 512 + 88), where six of the eight waves of a block
-    have no entries: node-lattice sites as above, so the force equals O-EW to
+    """Sizes below one block of 64 i-particles, one past it, and a j tile of
+    600 entries (9 * 64 + 24), where six of the sixteen waves of a block have
+    no entries: node-lattice sites as above, so the force equals O-EW to
     rounding. A lone particle feels nothing: its periodic images and the
     neutralising background balance by symmetry, and it has no pairs."""
     E, box = 32, 1.0
