@@ -32,11 +32,17 @@ def age(a, H0, Om, OL):
 
 
 def scale_factor(t, H0, Om, OL):
+    # bracket the root by doubling and halving (t(a) increases from 0)
     hi = 1.0
     while age(hi, H0, Om, OL) < t:
         hi *= 2.0
-    return optimize.brentq(lambda a: age(a, H0, Om, OL) - t, 0.0 + 1e-300, hi,
-                           xtol=1e-16, rtol=4e-16, maxiter=500)
+    lo = hi
+    while age(lo, H0, Om, OL) > t:
+        lo *= 0.5
+    if lo == hi:
+        return hi
+    return optimize.brentq(lambda a: age(a, H0, Om, OL) - t, lo, hi,
+                           xtol=1e-300, rtol=1e-15, maxiter=500)
 
 
 def kick_drift(a0, a1, H0, Om, OL):

@@ -296,3 +296,109 @@ def test_wrap_edges_and_kick():
     p = np.array([[1.0, 2.0]])
     f = np.array([[0.5, -4.0]], dtype=np.float32)
     assert np.all(integ.kick(p, f, 0.25) == np.array([[1.125, 1.0]]))
+
+
+# ---------------------------------------------------------------- pair count
+
+# Simple cubic lattice: the shells at squared distance 1, 2, 3, 4, 5 (in
+# units of the spacing) hold 6, 12, 8, 6, 24 points, so the coordination
+# number within a strict cutoff k * spacing is the sum over shells below k^2.
+_SC_SHELLS = [(1, 6), (2, 12), (3, 8), (4, 6), (5, 24)]
+
+
+@pytest.mark.parametrize("k,coord", [(1.5, 18), (1.8, 26), (2.1, 32), (2.3, 56)])
+def test_count_pairs_simple_cubic_coordination(k, coord):
+    """Ordered pairs on a periodic simple cubic lattice = N x coordination
+    number (each neighbour seen from both sides, the point itself excluded)."""
+    assert sum(c for d2, c in _SC_SHELLS if d2 < k * k) == coord
+    n_side = 8
+    lat = ics.lattice(n_side, offset=0.5)
+    r_c = k / n_side
+    assert pp.count_pairs(lat, 1.0, r_c) == n_side ** 3 * coord
+    # a subset of targets counts its own rows only
+    t = np.arange(0, n_side ** 3, 7)
+    assert pp.count_pairs(lat, 1.0, r_c, targets=t) == t.size * coord
+
+
+def test_count_pairs_brute_force_random():
+    """Against an all-pairs count written out here on a small random set with
+    two exact duplicates (separation 0 counts as a pair: j != i, r < r_c)."""
+    rng = np.random.default_rng(41)
+    pos = rng.random((3, 300)) * 1.3
+    pos[:, 7] = pos[:, 3]
+    pos[:, 250] = pos[:, 3]
+    box, r_c = 1.3, 0.21
+    n = pos.shape[1]
+    count = 0
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            d2 = 0.0
+            for a in range(3):
+                d = pos[a, i] - pos[a, j]
+                d -= box * math.floor(d / box + 0.5)
+                d2 += d * d
+            count += d2 < r_c * r_c
+    assert pp.count_pairs(pos, box, r_c) == count
+
+
+# ---------------------------------------------------------------- error metric
+
+def test_force_errors_hand_computed():
+    """Four particles: relative errors 0.1, 0.05 and 0.2, and one particle
+    whose reference force is below 1e-6 x the median (excluded from RMS and
+    max, kept in the global ratio)."""
+    ref = np.array([[1.0, 0.0, 0.0, 1e-9],
+                    [0.0, 2.0, 0.0, 0.0],
+                    [0.0, 0.0, 3.0, 0.0]])
+    F = np.array([[1.1, 0.0, 0.0, 5.0],
+                  [0.0, 2.0, 0.6, 0.0],
+                  [0.0, 0.1, 3.0, 0.0]])
+    e = metrics.force_errors(F, ref)
+    assert e["n"] == 4 and e["excluded"] == 1
+    assert e["max"] == pytest.approx(0.2, rel=1e-14)
+    assert e["rms"] == pytest.approx(math.sqrt((0.01 + 0.0025 + 0.04) / 3.0), rel=1e-14)
+    num = 0.01 + 0.01 + 0.36 + (5.0 - 1e-9) ** 2
+    assert e["global"] == pytest.approx(math.sqrt(num / (1.0 + 4.0 + 9.0 + 1e-18)), rel=1e-14)
+    # all references zero: nothing to compare, nothing reported as an error
+    z = metrics.force_errors(F, np.zeros_like(ref))
+    assert z["rms"] == 0.0 and z["max"] == 0.0 and z["excluded"] == 4
+
+
+# ---------------------------------------------------------------- background
+
+def test_oracle_cosmology_einstein_de_sitter():
+    """Omega_m = 1: t = 2 a^(3/2) / (3 H0); int da / (a^2 H) = 2 (sqrt a1 -
+    sqrt a0) / H0; int da / (a^3 H) = 2 (a0^-1/2 - a1^-1/2) / H0."""
+    from oracle import cosmology as oc
+    H0 = 0.7
+    for a in (1e-3, 0.02, 0.5, 1.0, 3.0):
+        t = 2.0 / (3.0 * H0) * a ** 1.5
+        assert oc.age(a, H0, 1.0, 0.0) == pytest.approx(t, rel=1e-12)
+        assert oc.scale_factor(t, H0, 1.0, 0.0) == pytest.approx(a, rel=1e-12)
+    for a0, a1 in ((0.01, 0.0125), (0.5, 1.0), (1e-3, 2e-3)):
+        ck, cd = oc.kick_drift(a0, a1, H0, 1.0, 0.0)
+        assert ck == pytest.approx(2.0 * (math.sqrt(a1) - math.sqrt(a0)) / H0, rel=1e-12)
+        assert cd == pytest.approx(2.0 * (1 / math.sqrt(a0) - 1 / math.sqrt(a1)) / H0, rel=1e-12)
+
+
+def test_oracle_cosmology_flat_lcdm_and_empty_and_lambda_only():
+    """Flat Lambda-CDM age: t = 2 asinh(sqrt(OL/Om) a^(3/2)) / (3 H0 sqrt OL).
+    Empty (Milne, all curvature): H = H0 / a, t = a / H0, int dt/a =
+    ln(a1/a0) / H0, int dt/a^2 = (1/a0 - 1/a1) / H0. Lambda only: H = H0,
+    int dt/a = (1/a0 - 1/a1) / H0, int dt/a^2 = (a0^-2 - a1^-2) / (2 H0)."""
+    from oracle import cosmology as oc
+    H0, Om, OL = 1.3, 0.3, 0.7
+    for a in (0.01, 0.1, 1.0):
+        ref = 2.0 / (3.0 * H0 * math.sqrt(OL)) * math.asinh(math.sqrt(OL / Om) * a ** 1.5)
+        assert oc.age(a, H0, Om, OL) == pytest.approx(ref, rel=1e-12)
+        assert oc.scale_factor(ref, H0, Om, OL) == pytest.approx(a, rel=1e-12)
+    for a0, a1 in ((0.02, 0.03), (0.5, 2.0)):
+        assert oc.age(a1, H0, 0.0, 0.0) == pytest.approx(a1 / H0, rel=1e-12)
+        ck, cd = oc.kick_drift(a0, a1, H0, 0.0, 0.0)
+        assert ck == pytest.approx(math.log(a1 / a0) / H0, rel=1e-12)
+        assert cd == pytest.approx((1 / a0 - 1 / a1) / H0, rel=1e-12)
+        ck, cd = oc.kick_drift(a0, a1, H0, 0.0, 1.0)
+        assert ck == pytest.approx((1 / a0 - 1 / a1) / H0, rel=1e-12)
+        assert cd == pytest.approx((a0 ** -2 - a1 ** -2) / (2 * H0), rel=1e-12)
