@@ -470,6 +470,70 @@ int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
   return count;
 }
 
+int plan_geometry(const p3m_params& q, int64_t n_max, p3m_plan* P) {
+  if (!is_pow2(q.grid_n) || q.grid_n < 16 || q.grid_n > 512) return P3M_EINVAL;
+  if (q.precision != P3M_FP64 && q.precision != P3M_FP32) return P3M_EINVAL;
+  if (q.fd_order != 2 && q.fd_order != 4) return P3M_EINVAL;
+  if (q.deconv_power != 0 && q.deconv_power != 2) return P3M_EINVAL;
+  if (!(q.box > 0) || !std::isfinite(q.box)) return P3M_EINVAL;
+  if (!(q.rs_cells > 0) || !std::isfinite(q.rs_cells)) return P3M_EINVAL;
+  if (!(q.cutoff_rs > 0) || !std::isfinite(q.cutoff_rs)) return P3M_EINVAL;
+  if (!(q.softening >= 0) || !std::isfinite(q.softening)) return P3M_EINVAL;
+  if (!std::isfinite(q.G)) return P3M_EINVAL;
+  if (n_max < 0 || n_max >= (int64_t{1} << 31)) return P3M_EINVAL;
+  if (q.adjoint != 0 && q.adjoint != 1) return P3M_EINVAL;
+  if (q.ewald_gridsize != 0 &&
+      (q.ewald_gridsize < 8 || q.ewald_gridsize > 512 || (q.ewald_gridsize & 1)))
+    return P3M_EINVAL;
+  const double h = q.box / q.grid_n;
+  const double r_s = q.rs_cells * h;
+  const double r_c = q.cutoff_rs * r_s;
+  if (!(r_c < 0.5 * q.box)) return P3M_ERANGE;
+  P->prm = q;
+  P->n_max = n_max;
+  P->ng = q.grid_n;
+  P->lg = ilog2(q.grid_n);
+  P->ncell = (int64_t)q.grid_n * q.grid_n * q.grid_n;
+  P->h = h;
+  P->r_s = r_s;
+  P->r_c = r_c;
+  P->eps = q.softening;
+  P->G = p3m_group_edge(n_max, q.grid_n);
+  P->lgG = ilog2(P->G);
+  P->ngd = q.grid_n / P->G;
+  P->ngroup = (int64_t)P->ngd * P->ngd * P->ngd;
+  P->nrows = stencil_rows(P->G, r_c / h, nullptr, 0);
+  P->max_items = P->ngroup + (n_max + kChunk - 1) / kChunk;
+  P->scan_tmp_len = std::max(scan_tmp_size(P->ncell), items_tmp_size(P->ngroup));
+  return P3M_OK;
+}
+
+hipError_t plan_upload_tables(p3m_plan* P, int32_t* rows_host) {
+  const p3m_params& q = P->prm;
+  stencil_rows(P->G, P->r_c / P->h, rows_host, P->nrows);
+  hipError_t err = hipMemcpyAsync(P->ws.rows, rows_host, sizeof(int4) * P->nrows,
+                                  hipMemcpyHostToDevice, P->stream);
+  if (err == hipSuccess) {
+    float tab[4 * (kSplitBins + 1)];
+    SplitMap m = split_table(q.cutoff_rs, q.softening / P->r_s, kSplitBins, tab);
+    P->tab_var = m.var;
+    P->tab_v0 = m.v0 * P->r_s;
+    P->tab_v1 = m.v1 * P->r_s;
+    err = hipMemcpyAsync(P->ws.split_tab, tab, sizeof(tab), hipMemcpyHostToDevice, P->stream);
+  }
+  if (err == hipSuccess) {
+    double tab64[kSplitCoef64 * (kSplitBins + 1)];
+    SplitMap m = split_table64(q.cutoff_rs, q.softening / P->r_s, tab64);
+    P->tab64_var = m.var;
+    P->tab64_v0 = m.v0 * P->r_s;
+    P->tab64_v1 = m.v1 * P->r_s;
+    P->tab64_exact = m.exact;
+    err = hipMemcpyAsync(P->ws.split_tab64, tab64, sizeof(tab64), hipMemcpyHostToDevice,
+                         P->stream);
+  }
+  return err;
+}
+
 }  // namespace p3m
 
 extern "C" {
@@ -546,47 +610,17 @@ int p3m_params_default(p3m_params* out, int32_t grid_n, double box) {
 int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_plan** out) {
   if (!prm || !out) return P3M_EINVAL;
   const p3m_params& q = *prm;
-  if (!is_pow2(q.grid_n) || q.grid_n < 16 || q.grid_n > 512) return P3M_EINVAL;
-  if (q.precision != P3M_FP64 && q.precision != P3M_FP32) return P3M_EINVAL;
-  if (q.fd_order != 2 && q.fd_order != 4) return P3M_EINVAL;
-  if (q.deconv_power != 0 && q.deconv_power != 2) return P3M_EINVAL;
-  if (!(q.box > 0) || !std::isfinite(q.box)) return P3M_EINVAL;
-  if (!(q.rs_cells > 0) || !std::isfinite(q.rs_cells)) return P3M_EINVAL;
-  if (!(q.cutoff_rs > 0) || !std::isfinite(q.cutoff_rs)) return P3M_EINVAL;
-  if (!(q.softening >= 0) || !std::isfinite(q.softening)) return P3M_EINVAL;
-  if (!std::isfinite(q.G)) return P3M_EINVAL;
-  if (n_max < 0 || n_max >= (int64_t{1} << 31)) return P3M_EINVAL;
-  if (q.adjoint != 0 && q.adjoint != 1) return P3M_EINVAL;
-  if (q.ewald_gridsize != 0 &&
-      (q.ewald_gridsize < 8 || q.ewald_gridsize > 512 || (q.ewald_gridsize & 1)))
-    return P3M_EINVAL;
-  const double h = q.box / q.grid_n;
-  const double r_s = q.rs_cells * h;
-  const double r_c = q.cutoff_rs * r_s;
-  if (!(r_c < 0.5 * q.box)) return P3M_ERANGE;
-
   p3m_plan* P = new (std::nothrow) p3m_plan;
   if (!P) return P3M_ENOMEM;
-  P->prm = q;
-  P->n_max = n_max;
+  const int st = p3m::plan_geometry(q, n_max, P);
+  if (st != P3M_OK) {
+    delete P;
+    return st;
+  }
   P->stream = (hipStream_t)hip_stream;
-  P->ng = q.grid_n;
-  P->lg = ilog2(q.grid_n);
-  P->ncell = (int64_t)q.grid_n * q.grid_n * q.grid_n;
-  P->h = h;
-  P->r_s = r_s;
-  P->r_c = r_c;
-  P->eps = q.softening;
-  P->G = p3m_group_edge(n_max, q.grid_n);
-  P->lgG = ilog2(P->G);
-  P->ngd = q.grid_n / P->G;
-  P->ngroup = (int64_t)P->ngd * P->ngd * P->ngd;
-  P->nrows = stencil_rows(P->G, r_c / h, nullptr, 0);
-  P->max_items = P->ngroup + (n_max + kChunk - 1) / kChunk;
   const int64_t nspec = (int64_t)q.grid_n * q.grid_n * (q.grid_n / 2 + 1);
   const size_t real = q.precision == P3M_FP32 ? sizeof(float) : sizeof(double);
   const int64_t nn = n_max > 0 ? n_max : 1;
-  P->scan_tmp_len = std::max(scan_tmp_size(P->ncell), items_tmp_size(P->ngroup));
 
   hipError_t err = hipGetDevice(&P->device);
   Workspace& W = P->ws;
@@ -632,26 +666,8 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
       delete P;
       return P3M_ENOMEM;
     }
-    stencil_rows(P->G, r_c / h, rows, P->nrows);
-    err = hipMemcpy(W.rows, rows, sizeof(int4) * P->nrows, hipMemcpyHostToDevice);
+    err = p3m::plan_upload_tables(P, rows);
     delete[] rows;
-  }
-  if (err == hipSuccess) {
-    float tab[4 * (kSplitBins + 1)];
-    SplitMap m = split_table(q.cutoff_rs, q.softening / r_s, kSplitBins, tab);
-    P->tab_var = m.var;
-    P->tab_v0 = m.v0 * r_s;
-    P->tab_v1 = m.v1 * r_s;
-    err = hipMemcpy(W.split_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
-  }
-  if (err == hipSuccess) {
-    double tab64[kSplitCoef64 * (kSplitBins + 1)];
-    SplitMap m = split_table64(q.cutoff_rs, q.softening / r_s, tab64);
-    P->tab64_var = m.var;
-    P->tab64_v0 = m.v0 * r_s;
-    P->tab64_v1 = m.v1 * r_s;
-    P->tab64_exact = m.exact;
-    err = hipMemcpy(W.split_tab64, tab64, sizeof(tab64), hipMemcpyHostToDevice);
   }
   if (err == hipSuccess)
     err = q.precision == P3M_FP32 ? launch_tables<float>(P) : launch_tables<double>(P);

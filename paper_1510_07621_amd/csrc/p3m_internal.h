@@ -160,6 +160,15 @@ hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double*
 
 // Host geometry helpers.
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap);
+// Validation of the parameters (the checks and status codes of
+// p3m_plan_create) and the plan's geometry: grid, split and cutoff lengths,
+// i-group edge, stencil row count, work-list bound. Allocates nothing.
+int plan_geometry(const p3m_params& q, int64_t n_max, p3m_plan* P);
+// The stencil rows (computed into rows_host, P->nrows entries of 4 int32)
+// and the split-factor tables copied into the plan's workspace on its
+// stream (pageable host sources: each copy has read its source on return);
+// sets the plan's table maps.
+hipError_t plan_upload_tables(p3m_plan* P, int32_t* rows_host);
 // Split-factor table: out[c * (bins + 1) + k] is coefficient c of bin k of
 // the cubic pieces over v in [v0, v1] (units of r_s); var 0: v = r / r_s,
 // var 1: v = sqrt(r^2 + eps^2) / r_s.

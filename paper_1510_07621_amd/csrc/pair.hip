@@ -86,7 +86,7 @@ struct PairArgs {
   float tab_s, tab_s2, tab_e2, tab_off;
   // Force over the softened-distance table: positions scaled by s, so
   // rho^2 starts from e2 = (s eps)^2 (floored: FP32 at tab_e2's 1e-12, FP64
-  // at 1e-200) and is tested against s^2 r_c^2 + e2.
+  // at 1e-100) and is tested against s^2 r_c^2 + e2.
   float rho_e2, rho_cut2;               // FP32
   double rho_e2d, rho_cut2d;            // FP64
   double rho_inv2rs;                    // FP64: 1 / (2 r_s s), for the series
@@ -218,9 +218,10 @@ __device__ __forceinline__ double pair_weight(double r2, const PairArgs<double>&
 // The same weight (softened-distance table) from q = s^2 (r^2 + eps^2),
 // formed from positions already scaled by s, so the bin coordinate is
 // q rsqrt(q) - s v0 and the weight f / (s rho)^3; r^2 itself is formed only
-// for the series pieces. q starts from (s eps)^2 floored at 1e-200, so the
-// weight is finite for every pair (at most 1e300) and a self or coincident
-// pair contributes it times a zero separation. The bin coordinate lies in
+// for the series pieces. q starts from (s eps)^2 floored at 1e-100, so the
+// weight is finite for every pair (at most 1e150, leaving room for a
+// per-particle mass factor up to 1e150) and a self or coincident pair
+// contributes it times a zero separation. The bin coordinate lies in
 // [0, kSplitBins] without clamping: the table starts a hair below s eps and
 // the cutoff test bounds q by s^2 (r_c^2 + eps^2), its end.
 __device__ __forceinline__ double pair_weight_rho(double q, const PairArgs<double>& A,
@@ -552,16 +553,19 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
       __syncthreads();
       // lane (set, stream) takes staged entries st, st + ns, ...; the trip
       // count is wave-uniform; reads past the end (at most ns - 1) hit the
-      // sentinels, and empty slots sit at +kFar, so both fail the cutoff test
+      // sentinels, and empty slots sit at +kFar, so both fail the cutoff test.
+      // Lanes beyond the streams (st >= ns, all slots empty) read stream 0's
+      // entries, so no read passes the sentinels.
       const int iters = (cn + ns - 1) / ns;
-      const T4* jp = S.jb + st;
+      const int st_r = active ? st : 0;
+      const T4* jp = S.jb + st_r;
       if constexpr (VJP) {
         // sentinel slots carry no cotangent; their separations fail the test
-        const T4* lp = S.jl + st;
+        const T4* lp = S.jl + st_r;
 #pragma unroll 2
         for (int t = 0; t < iters; ++t) {
           const T4& pj = jp[t * ns];
-          const T4 lj = t * ns + st < cn ? lp[t * ns] : T4{};
+          const T4 lj = t * ns + st_r < cn ? lp[t * ns] : T4{};
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const T dx = xi[u] - pj.x, dy = yi[u] - pj.y, dz = zi[u] - pj.z;
@@ -779,7 +783,7 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
     A.split_tab = W.split_tab64;
     A.tab_s64 = s;
     A.tab_off64 = s * P->tab64_v0;
-    A.rho_e2d = std::max(s * s * P->eps * P->eps, 1e-200);
+    A.rho_e2d = std::max(s * s * P->eps * P->eps, 1e-100);
     A.rho_cut2d = s * s * P->r_c * P->r_c + A.rho_e2d;
     A.rho_inv2rs = 1.0 / (2.0 * P->r_s * s);
     A.wscale_rho = -P->prm.G * s * s;
