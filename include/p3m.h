@@ -54,6 +54,7 @@ extern "C" {
 #define P3M_ENOMEM  -2  /* device allocation failed in p3m_plan_create        */
 #define P3M_EHIP    -3  /* a HIP runtime call or kernel launch failed          */
 #define P3M_ERANGE  -4  /* r_c >= box/2 (minimum image insufficient)           */
+#define P3M_ESIZE   -5  /* sizes beyond the fixed workspace of pp_force_noalloc */
 
 /* Arithmetic of the force path (particle storage, kick and drift stay FP64). */
 #define P3M_FP64     0  /* pair loop, FFT and grids in double precision        */
@@ -267,6 +268,33 @@ int p3m_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar, const doubl
 #define P3M_NUM_STAGES     5
 int p3m_set_timing(p3m_plan* plan, int32_t capacity);
 int p3m_stage_times(p3m_plan* plan, double* ms_out, int32_t n_stages);
+
+/* Short-range (PP) force without a plan, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc). The same force as pp_force on a plan made from
+ * `params` for n particles, computed by the same kernels, with every pair
+ * evaluated from both sides. The call allocates nothing: its workspace is
+ * one fixed device array of 12 MiB per GPU, held from the library's first
+ * such call on that GPU until the process ends; the stencil rows and
+ * split-factor tables are computed on the host and copied into it on
+ * hip_stream (from host memory the call owns) before the kernels run.
+ *   params      as for p3m_plan_create (all of it validated the same way;
+ *               fd_order, deconv_power, adjoint and ewald_gridsize unused)
+ *   n           0 <= n <= P3M_NOALLOC_MAX_N
+ *   pos, mass, mass_scalar, force, force_fp32   as for pp_force
+ *   hip_stream  the stream the work runs on (NULL = the null stream)
+ * Limits: n <= P3M_NOALLOC_MAX_N, params->grid_n <= P3M_NOALLOC_MAX_GRID and
+ * at most 4096 stencil rows (r_c up to about 30 cells); beyond them
+ * P3M_ESIZE before anything is enqueued. Every call on a GPU shares that
+ * GPU's array, which keeps the last call's contents (the call clears what
+ * must start at zero): calls that overlap on one GPU (other streams, other
+ * host threads between enqueue and completion) race. Host threads are
+ * serialised while they enqueue. n == 0 is a successful no-op. */
+#define P3M_NOALLOC_MAX_N    65536
+#define P3M_NOALLOC_MAX_GRID 64
+int pp_force_noalloc(const p3m_params* params, int64_t n, const double* pos,
+                     const double* mass, double mass_scalar, void* force,
+                     int32_t force_fp32, void* hip_stream);
 
 /* Static text for a status code ("unknown status" for others). */
 const char* p3m_strerror(int status);

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # P3M_LIBRARY selects another build of the same library (e.g. a debug build).
 LIB_PATH = os.environ.get("P3M_LIBRARY") or os.path.join(_HERE, "libp3m.so")
 
-P3M_OK, P3M_EINVAL, P3M_ENOMEM, P3M_EHIP, P3M_ERANGE = 0, -1, -2, -3, -4
+P3M_OK, P3M_EINVAL, P3M_ENOMEM, P3M_EHIP, P3M_ERANGE, P3M_ESIZE = 0, -1, -2, -3, -4, -5
 P3M_FP64, P3M_FP32 = 0, 1
 STAGES = ("bin", "deposit", "fft", "interp", "pp")
 
@@ -61,6 +61,8 @@ def _load():
         "pm_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "pp_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "p3m_pair_count": (ctypes.c_int, [vp, i64, vp, vp]),
+        "pp_force_noalloc": (ctypes.c_int, [ctypes.POINTER(P3MParams), i64, vp, vp, dbl, vp,
+                                            i32, vp]),
         "p3m_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
         "pp_ewald_force": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32]),
         "p3m_ewald_correction": (ctypes.c_int, [vp, i64, vp, vp]),
@@ -105,7 +107,7 @@ def _check(status: int, what: str) -> None:
     if status == P3M_OK:
         return
     msg = f"{what}: {strerror(status)} (status {status})"
-    if status in (P3M_EINVAL, P3M_ERANGE):
+    if status in (P3M_EINVAL, P3M_ERANGE, P3M_ESIZE):
         raise ValueError(msg)
     raise RuntimeError(msg)
 
@@ -251,6 +253,24 @@ class Params:
                          float(self.rs_cells), float(self.cutoff_rs),
                          float(self.softening), float(self.G), 1 if self.adjoint else 0,
                          int(self.ewald_gridsize))
+
+
+def pp_force_noalloc(params: Params, pos, mass=None, out=None, fp32_out=False):
+    """pp_force without a plan (the library's fixed workspace; no device
+    allocation inside the call): short-range force, shape (3, n)."""
+    n = _vec3(pos, "pos")
+    m, ms = _mass(mass, n)
+    if out is None:
+        out = torch.empty((3, n), dtype=torch.float32 if fp32_out else torch.float64,
+                          device=pos.device)
+    else:
+        fp32_out = out.dtype == torch.float32
+        if _vec3(out, "out", out.dtype) != n or out.dtype not in (torch.float32, torch.float64):
+            raise ValueError("out must be (3, n) float32 or float64")
+    c = params.to_c()
+    _check(_lib.pp_force_noalloc(ctypes.byref(c), n, _ptr(pos), _ptr(m), ms, _ptr(out),
+                                 1 if fp32_out else 0, _stream_ptr()), "pp_force_noalloc")
+    return out
 
 
 class Plan:

@@ -894,6 +894,7 @@ const char* p3m_strerror(int status) {
     case P3M_ENOMEM: return "out of device memory";
     case P3M_EHIP: return "HIP runtime error";
     case P3M_ERANGE: return "cutoff must be below half the box (minimum image)";
+    case P3M_ESIZE: return "sizes beyond the fixed workspace of the allocation-free call";
     default: return "unknown status";
   }
 }

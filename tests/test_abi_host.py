@@ -116,6 +116,28 @@ def test_calls_on_null_plan_and_bad_arguments(b):
     assert st == -1
 
 
+def test_noalloc_argument_errors_before_any_device_call(b):
+    """pp_force_noalloc rejects bad arguments and sizes beyond its fixed
+    workspace before it touches the device (these paths run without a GPU)."""
+    L = b._lib
+    p = b.Params(grid_n=32, softening=1e-3).to_c()
+    assert L.pp_force_noalloc(None, 10, 1, None, 1.0, 2, 0, None) == -1
+    assert L.pp_force_noalloc(ctypes.byref(p), -1, 1, None, 1.0, 2, 0, None) == -1
+    assert L.pp_force_noalloc(ctypes.byref(p), 65537, 1, None, 1.0, 2, 0, None) == -5
+    assert L.pp_force_noalloc(ctypes.byref(p), 0, None, None, 1.0, None, 0, None) == 0
+    assert L.pp_force_noalloc(ctypes.byref(p), 10, None, None, 1.0, 2, 0, None) == -1
+    assert L.pp_force_noalloc(ctypes.byref(p), 10, 1, None, float("nan"), 2, 0, None) == -1
+    # force overlapping pos
+    assert L.pp_force_noalloc(ctypes.byref(p), 10, 4096, None, 1.0, 4096 + 80, 0, None) == -1
+    big = b.Params(grid_n=128).to_c()
+    assert L.pp_force_noalloc(ctypes.byref(big), 10, 1, None, 1.0, 4096, 0, None) == -5
+    bad = b.Params(grid_n=24).to_c()
+    assert L.pp_force_noalloc(ctypes.byref(bad), 10, 1, None, 1.0, 4096, 0, None) == -1
+    far = b.Params(grid_n=16, rs_cells=2.0, cutoff_rs=4.0).to_c()     # r_c = box / 2
+    assert L.pp_force_noalloc(ctypes.byref(far), 10, 1, None, 1.0, 4096, 0, None) == -4
+    assert "fixed workspace" in b.strerror(-5)
+
+
 def test_strerror(b):
     assert b.strerror(0) == "success"
     assert "invalid" in b.strerror(-1)
