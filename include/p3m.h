@@ -74,6 +74,15 @@ typedef struct p3m_params {
   int32_t adjoint;      /* 1: also allocate the workspace of the *_force_vjp calls   */
   int32_t ewald_gridsize; /* ewald_gridsize: 0, or even in 8..512 to tabulate the
                              Ewald correction of pp_ewald_force                    */
+  int32_t pair_partials;  /* short-range sum: 0 evaluates every pair from both
+                             sides; > 0 evaluates a pair of particles in two
+                             dense groups (more than 128 particles each) once
+                             (the force on one is minus that on the other) and
+                             keeps the reactions as partials, of which the plan
+                             holds pair_partials per particle (80 suits strongly
+                             clustered sets); a call that needs more falls back
+                             to both sides. Pays on clustered sets (256^3
+                             Plummer mix: -7 %), not on smooth ones            */
 } p3m_params;
 
 /* Opaque plan: derived geometry, device workspace, and optional stage timers. */
@@ -81,7 +90,8 @@ typedef struct p3m_plan p3m_plan;
 
 /* Fill *out with the documented defaults for a grid of grid_n^3 cells in a
  * box of side box: FP32, fd_order 4, deconv_power 2, rs_cells 1.25,
- * cutoff_rs 4.5, softening 0, G 1, adjoint 0, ewald_gridsize 0. Returns
+ * cutoff_rs 4.5, softening 0, G 1, adjoint 0, ewald_gridsize 0,
+ * pair_partials 0. Returns
  * P3M_EINVAL for a null out. */
 int p3m_params_default(p3m_params* out, int32_t grid_n, double box);
 
@@ -92,13 +102,19 @@ int p3m_params_default(p3m_params* out, int32_t grid_n, double box);
  * ewald_gridsize not 0 or even in 8..512,
  * n_max < 0 or n_max >= 2^31; ERANGE when r_c >= box/2), then allocates the
  * workspace (with adjoint = 1 also that of the VJP calls: one more real grid,
- * three cotangent grids and a sorted cotangent array)
- * (ENOMEM on failure; nothing is leaked). *out is set only on success. */
+ * three cotangent grids and a sorted cotangent array; with pair_partials > 0
+ * the reaction partials, pair_partials n_max + 65536 of 3 reals each (at 80:
+ * 0.96 KB (FP32) or 1.9 KB (FP64) per particle), plus per-group offsets; if
+ * that allocation fails the plan evaluates every pair from both sides)
+ * (ENOMEM on failure; nothing is leaked). *out is set only on success.
+ * CONCEPT User's Guide Ch. 5 (PM_gridsize, PM_scale, P3M_cutoff,
+ * softeningfactors, boxsize) for the parameters. */
 int p3m_plan_create(const p3m_params* params, int64_t n_max, void* hip_stream,
                     p3m_plan** out);
 
-/* Release the plan and its workspace. Synchronises the plan's stream first.
- * A null plan is a no-op returning P3M_OK. */
+/* Release the plan and its workspace (the counterpart of p3m_plan_create).
+ * Synchronises the plan's stream first. A null plan is a no-op returning
+ * P3M_OK. */
 int p3m_plan_destroy(p3m_plan* plan);
 
 /* Change the stream later calls on this plan enqueue on. */

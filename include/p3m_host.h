@@ -25,6 +25,19 @@ extern "C" {
 int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out,
                          int32_t cap);
 
+/* The same stencil cut into group segments, for the pair sum that evaluates
+ * a pair of particles in two dense groups once (the force on one is minus
+ * that on the other; Newton's third law). A cell at offset d from the
+ * group's first cell lies in the group offset o = floor(d / g) (per axis);
+ * every row is cut where its z range crosses a multiple of g, and each piece
+ * carries the lexicographic sign of its (ox, oy, oz): +1, -1, or 0 for the
+ * group itself. Of two distinct groups, exactly one sees the other at a
+ * positive offset. Entries of 4 int32: (dx & 0xffff) | (dy << 16), dz_lo,
+ * dz_hi, sign; in the order of p3m_stencil_rows, pieces by increasing z.
+ * Writes min(count, cap) entries, returns the count or P3M_EINVAL as
+ * p3m_stencil_rows. */
+int32_t p3m_segment_rows(int32_t g, double radius_cells, int32_t* rows_out, int32_t cap);
+
 /* Table of the split factor f = erfc(u) + (2u/sqrt(pi)) exp(-u^2),
  * u = r / (2 r_s), that the FP32 pair sum evaluates (P3M short-range force,
  * CONCEPT User's Guide, Ch. 5: P3M_scale, P3M_cutoff, softening). Arguments:

@@ -36,6 +36,7 @@ class P3MParams(ctypes.Structure):
         ("G", ctypes.c_double),
         ("adjoint", ctypes.c_int32),
         ("ewald_gridsize", ctypes.c_int32),
+        ("pair_partials", ctypes.c_int32),
     ]
 
 
@@ -78,6 +79,7 @@ def _load():
         "p3m_stage_times": (ctypes.c_int, [vp, ctypes.POINTER(dbl), i32]),
         "p3m_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "p3m_stencil_rows": (i32, [i32, dbl, ctypes.POINTER(i32), i32]),
+        "p3m_segment_rows": (i32, [i32, dbl, ctypes.POINTER(i32), i32]),
         "p3m_group_edge": (i32, [i64, i32]),
         "p3m_split_table": (i32, [dbl, dbl, ctypes.POINTER(ctypes.c_float), i32,
                                   ctypes.POINTER(dbl)]),
@@ -145,6 +147,21 @@ def stencil_rows(g: int, radius_cells: float):
     buf = (ctypes.c_int32 * (4 * n))()
     _lib.p3m_stencil_rows(g, radius_cells, buf, n)
     return [tuple(buf[4 * k:4 * k + 4]) for k in range(n)]
+
+
+def segment_rows(g: int, radius_cells: float):
+    """The stencil cut into group segments (dx, dy, dz_lo, dz_hi, sign), sign
+    the lexicographic sign of the segment's group offset (0: the group)."""
+    n = _lib.p3m_segment_rows(g, radius_cells, None, 0)
+    _check(min(n, 0), "p3m_segment_rows")
+    buf = (ctypes.c_int32 * (4 * max(n, 1)))()
+    _lib.p3m_segment_rows(g, radius_cells, buf, n)
+    out = []
+    for k in range(n):
+        p = buf[4 * k]
+        dx = ((p & 0xffff) ^ 0x8000) - 0x8000
+        out.append((dx, p >> 16, buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]))
+    return out
 
 
 def group_edge(n: int, grid_n: int) -> int:
@@ -243,6 +260,8 @@ class Params:
     deconv_power: int = 2
     adjoint: bool = False        # also allocate the workspace of the VJP calls
     ewald_gridsize: int = 0      # > 0: tabulate the Ewald correction (pp_ewald_force)
+    pair_partials: int = 0       # < 0: every pair from both sides; else partials per
+                                 # particle of the one-sided sum (0: the default)
 
     def to_c(self) -> P3MParams:
         if self.precision not in ("fp32", "fp64"):
@@ -252,7 +271,7 @@ class Params:
                          int(self.fd_order), int(self.deconv_power), float(self.box),
                          float(self.rs_cells), float(self.cutoff_rs),
                          float(self.softening), float(self.G), 1 if self.adjoint else 0,
-                         int(self.ewald_gridsize))
+                         int(self.ewald_gridsize), int(self.pair_partials))
 
 
 def pp_force_noalloc(params: Params, pos, mass=None, out=None, fp32_out=False):

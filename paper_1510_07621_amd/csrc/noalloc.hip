@@ -24,7 +24,7 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 std::mutex g_mutex;                       // the address table and the host row buffer
 void* g_scratch[kMaxDevices] = {};
-int32_t g_rows[4 * kMaxRows];
+int32_t g_rows[8 * kMaxRows];
 
 // Device address of this device's scratch array (looked up once per device,
 // with that device current).

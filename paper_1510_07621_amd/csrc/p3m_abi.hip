@@ -44,7 +44,9 @@ void free_workspace(p3m_plan* P) {
   void* ptrs[] = {W.key,  W.rank,   W.count,  W.start, W.perm,  W.skey,    W.scan_tmp,
                   W.gchunk, W.goff, W.items,  W.rows,  W.rec,   W.acc_pm,  W.grid,
                   W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.split_tab64, W.lam,
-                  W.grid2, W.lam_grid, W.power_acc, W.ewald_tab, W.ewald_zpair};
+                  W.grid2, W.lam_grid, W.power_acc, W.ewald_tab, W.ewald_zpair,
+                  W.segrows, W.prows, W.pbrows, W.pboff, W.rowoff, W.gipre, W.gntot,
+                  W.gtot, W.gbase, W.gscan_tmp, W.rpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -436,13 +438,17 @@ SplitMap split_table64(double cutoff_rs, double soft_rs, double* out) {
   return m;
 }
 
-int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
+// The stencil rows of a g^3-cell group, all of them (half = false) or the
+// half of them with a lexicographically positive group offset.
+static int stencil_rows_of(int g, double radius_cells, bool half, int32_t* out, int cap) {
   if (g < 1 || !(radius_cells > 0) || !std::isfinite(radius_cells)) return P3M_EINVAL;
   // A cell can hold a partner closer than r_c iff its gap to the group box is
   // below r_c; the small margin keeps rounding in the pair test harmless.
   const double R = radius_cells + 1e-9;
   const double R2 = R * R;
   const int reach = (int)std::ceil(R) + 1;
+  // group offset of a cell offset d (floor division by g)
+  auto gof = [g](int d) { return d >= 0 ? d / g : -((-d + g - 1) / g); };
   int count = 0;
   for (int dx = -reach; dx < g + reach; ++dx) {
     int gx = axis_gap(dx, g);
@@ -458,6 +464,12 @@ int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
           hi = dz;
         }
       }
+      if (half) {
+        const int ox = gof(dx), oy = gof(dy);
+        if (ox < 0 || (ox == 0 && oy < 0)) continue;   // lexicographically negative columns
+        if (ox == 0 && oy == 0) lo = std::max(lo, g);  // own column: the groups above only
+        if (lo > hi) continue;
+      }
       if (count < cap && out) {
         out[4 * count + 0] = dx;
         out[4 * count + 1] = dy;
@@ -467,6 +479,55 @@ int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
       ++count;
     }
   }
+  return count;
+}
+
+int stencil_rows(int g, double radius_cells, int32_t* out, int cap) {
+  return stencil_rows_of(g, radius_cells, false, out, cap);
+}
+
+int segment_rows(int g, double radius_cells, int32_t* out, int cap, int* npos) {
+  const int nfull = stencil_rows_of(g, radius_cells, false, nullptr, 0);
+  if (nfull < 0) return nfull;
+  const double R = radius_cells + 1e-9;
+  const double R2 = R * R;
+  const int reach = (int)std::ceil(R) + 1;
+  auto gof = [g](int d) { return d >= 0 ? d / g : -((-d + g - 1) / g); };
+  int count = 0, pos = 0;
+  // the full stencil's rows in their order (as stencil_rows_of walks them),
+  // each cut where its z range crosses a group boundary
+  for (int dx = -reach; dx < g + reach; ++dx) {
+    int gx = axis_gap(dx, g);
+    for (int dy = -reach; dy < g + reach; ++dy) {
+      int gy = axis_gap(dy, g);
+      double gxy = double(gx) * gx + double(gy) * gy;
+      if (!(gxy < R2)) continue;
+      int lo = 0, hi = -1;
+      for (int dz = -reach; dz < g + reach; ++dz) {
+        int gz = axis_gap(dz, g);
+        if (gxy + double(gz) * gz < R2) {
+          if (hi < lo) lo = dz;
+          hi = dz;
+        }
+      }
+      const int ox = gof(dx), oy = gof(dy);
+      for (int oz = gof(lo); oz <= gof(hi); ++oz) {
+        const int zlo = std::max(lo, oz * g), zhi = std::min(hi, oz * g + g - 1);
+        const int sign = ox != 0 ? (ox > 0 ? 1 : -1)
+                       : oy != 0 ? (oy > 0 ? 1 : -1)
+                       : oz != 0 ? (oz > 0 ? 1 : -1) : 0;
+        if (count < cap && out) {
+          out[4 * count + 0] = (dx & 0xffff) | (int32_t)((uint32_t)dy << 16);
+          out[4 * count + 1] = zlo;
+          out[4 * count + 2] = zhi;
+          out[4 * count + 3] = sign;
+        }
+        ++count;
+        pos += sign > 0;
+      }
+    }
+  }
+  if (npos) *npos = pos;
   return count;
 }
 
@@ -482,6 +543,7 @@ int plan_geometry(const p3m_params& q, int64_t n_max, p3m_plan* P) {
   if (!std::isfinite(q.G)) return P3M_EINVAL;
   if (n_max < 0 || n_max >= (int64_t{1} << 31)) return P3M_EINVAL;
   if (q.adjoint != 0 && q.adjoint != 1) return P3M_EINVAL;
+  if (q.pair_partials < 0) return P3M_EINVAL;
   if (q.ewald_gridsize != 0 &&
       (q.ewald_gridsize < 8 || q.ewald_gridsize > 512 || (q.ewald_gridsize & 1)))
     return P3M_EINVAL;
@@ -503,6 +565,8 @@ int plan_geometry(const p3m_params& q, int64_t n_max, p3m_plan* P) {
   P->ngd = q.grid_n / P->G;
   P->ngroup = (int64_t)P->ngd * P->ngd * P->ngd;
   P->nrows = stencil_rows(P->G, r_c / h, nullptr, 0);
+  P->nseg = segment_rows(P->G, r_c / h, nullptr, 0, &P->npos);
+  if (P->nseg < 0) return P->nseg;
   P->max_items = P->ngroup + (n_max + kChunk - 1) / kChunk;
   P->scan_tmp_len = std::max(scan_tmp_size(P->ncell), items_tmp_size(P->ngroup));
   return P3M_OK;
@@ -513,6 +577,48 @@ hipError_t plan_upload_tables(p3m_plan* P, int32_t* rows_host) {
   stencil_rows(P->G, P->r_c / P->h, rows_host, P->nrows);
   hipError_t err = hipMemcpyAsync(P->ws.rows, rows_host, sizeof(int4) * P->nrows,
                                   hipMemcpyHostToDevice, P->stream);
+  if (err == hipSuccess && P->ws.segrows) {
+    // the stencil cut into group segments (staging order), its positive
+    // segments in the same order, and those bucketed by the class
+    // (dx mod G, dy mod G) of their column offset with their index among
+    // the positive ones (for the gather of the reactions: a particle in a
+    // column of class (a, b) lies in segments of that class only)
+    int32_t* seg = rows_host + 4 * (size_t)P->nrows;
+    int32_t* pos = seg + 4 * (size_t)P->nseg;
+    int32_t* pb = pos + 4 * (size_t)P->npos;
+    int32_t* off = pb + 4 * (size_t)P->npos;
+    segment_rows(P->G, P->r_c / P->h, seg, P->nseg, nullptr);
+    int k = 0;
+    for (int r = 0; r < P->nseg; ++r)
+      if (seg[4 * r + 3] > 0) {
+        for (int c = 0; c < 4; ++c) pos[4 * k + c] = seg[4 * r + c];
+        pos[4 * k + 3] = k;
+        ++k;
+      }
+    const int G = P->G, nb = G * G;
+    int m = 0;
+    for (int b = 0; b < nb; ++b) {
+      off[b] = m;
+      for (int r = 0; r < P->npos; ++r) {
+        const int dx = (int)(int16_t)(pos[4 * r] & 0xffff), dy = pos[4 * r] >> 16;
+        if ((((dx & (G - 1)) * G) | (dy & (G - 1))) != b) continue;
+        for (int c = 0; c < 4; ++c) pb[4 * m + c] = pos[4 * r + c];
+        ++m;
+      }
+    }
+    off[nb] = m;
+    err = hipMemcpyAsync(P->ws.segrows, seg, sizeof(int4) * P->nseg, hipMemcpyHostToDevice,
+                         P->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(P->ws.prows, pos, sizeof(int4) * P->npos, hipMemcpyHostToDevice,
+                           P->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(P->ws.pbrows, pb, sizeof(int4) * P->npos, hipMemcpyHostToDevice,
+                           P->stream);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(P->ws.pboff, off, sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice,
+                           P->stream);
+  }
   if (err == hipSuccess) {
     float tab[4 * (kSplitBins + 1)];
     SplitMap m = split_table(q.cutoff_rs, q.softening / P->r_s, kSplitBins, tab);
@@ -541,6 +647,11 @@ extern "C" {
 int32_t p3m_stencil_rows(int32_t g, double radius_cells, int32_t* rows_out, int32_t cap) {
   if (cap < 0 || (cap > 0 && !rows_out)) return P3M_EINVAL;
   return p3m::stencil_rows(g, radius_cells, rows_out, cap);
+}
+
+int32_t p3m_segment_rows(int32_t g, double radius_cells, int32_t* rows_out, int32_t cap) {
+  if (cap < 0 || (cap > 0 && !rows_out)) return P3M_EINVAL;
+  return p3m::segment_rows(g, radius_cells, rows_out, cap, nullptr);
 }
 
 int32_t p3m_split_table(double cutoff_rs, double softening_rs, float* out, int32_t cap,
@@ -604,6 +715,7 @@ int p3m_params_default(p3m_params* out, int32_t grid_n, double box) {
   out->cutoff_rs = 4.5;
   out->softening = 0.0;
   out->G = 1.0;
+  out->pair_partials = 0;
   return P3M_OK;
 }
 
@@ -655,12 +767,37 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
     W.grid2 = dev_alloc<unsigned char>(P->ncell * real, err);
     W.lam_grid = dev_alloc<unsigned char>(3 * P->ncell * real, err);
   }
+  // the one-sided pair sum: half stencil, per-group offsets, partials; if the
+  // partials do not fit, the plan sums every pair from both sides
+  if (err == hipSuccess && q.pair_partials > 0 && P->npos > 0) {
+    W.segrows = dev_alloc<int4>(P->nseg, err);
+    W.prows = dev_alloc<int4>(P->npos, err);
+    W.pbrows = dev_alloc<int4>(P->npos, err);
+    W.pboff = dev_alloc<int32_t>(P->G * P->G + 1, err);
+    W.gipre = dev_alloc<int32_t>(P->ngroup * P->G * P->G, err);
+    W.rowoff = dev_alloc<int32_t>(P->ngroup * (P->npos + 1), err);
+    W.gntot = dev_alloc<int32_t>(P->ngroup, err);
+    W.gtot = dev_alloc<long long>(P->ngroup, err);
+    W.gbase = dev_alloc<long long>(P->ngroup + 1, err);
+    W.gscan_tmp = dev_alloc<long long>(react_scan_tmp_size(P->ngroup), err);
+    const int64_t cap = (int64_t)q.pair_partials * nn + kPartialsSlack;
+    if (err == hipSuccess) {
+      void* p = nullptr;
+      if (hipMalloc(&p, (size_t)cap * 3 * real) == hipSuccess) {
+        W.rpart = p;
+        P->rcap = cap;
+      } else {
+        (void)hipGetLastError();          // clear the failed allocation's error
+      }
+    }
+  }
   // the P3M force's second stream (default priority) and its fork / join events
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
   if (err == hipSuccess) {
-    int32_t* rows = new (std::nothrow) int32_t[4 * (size_t)P->nrows];
+    int32_t* rows =
+        new (std::nothrow) int32_t[4 * (size_t)(P->nrows + P->nseg + 2 * P->npos) + 17];
     if (!rows) {
       free_workspace(P);
       delete P;

@@ -29,6 +29,21 @@ constexpr int kSplitBins = 64;    // pieces of the split-factor tables
 constexpr int kSplitCoef64 = 7;   // coefficients per piece of the FP64 table (degree 6)
 constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
 constexpr int kMaxPowerBins = 512;     // shells of the power spectrum
+// Reaction partials a plan holds for the one-sided pair sum by default, per
+// particle and in all (at the workloads' settings 34 per particle on a
+// displaced lattice, 64 on the 256^3 Plummer mix).
+constexpr int64_t kPartialsPerParticle = 80;
+// A group is dense (pairs with other dense groups evaluated once) above
+// this many particles: two chunks of items. (Above one chunk, 64, the
+// displaced lattice at one particle per cell made 40 % of its groups dense
+// and its second, small chunks wrote as many partials as the first: 2.63 ->
+// 3.18 ms for its short-range sum, while the clustered 256^3 set gained
+// only 38.9 -> 38.2 ms.)
+#ifndef P3M_DENSE_MIN
+#define P3M_DENSE_MIN 128
+#endif
+constexpr int kDenseMin = P3M_DENSE_MIN;
+constexpr int64_t kPartialsSlack = 65536;
 
 // One particle in cell order: offsets from its cell's lower corner and mass.
 // (x, y, z, m) as float4 (FP32 path) or double4 (FP64 path).
@@ -57,6 +72,21 @@ struct Workspace {
   double* power_acc = nullptr;  // [3 * kMaxPowerBins + 2] power-spectrum sums
   void* ewald_tab = nullptr;    // [(E/2+1)^3] double4 Ewald correction octant (E > 0)
   void* ewald_zpair = nullptr;  // [(E/2+1)^2 (E/2)][3] double2: z-adjacent node pairs of it
+  // one-sided pair sum between dense groups (Newton's third law; plans
+  // with rcap > 0)
+  int4* segrows = nullptr;      // [nseg]    stencil cut into group segments, staging order:
+                                //           (dx & 0xffff | dy << 16, dz_lo, dz_hi, sign)
+  int4* prows = nullptr;        // [npos]    the positive segments (sign > 0), in that order
+  int4* pbrows = nullptr;       // [npos]    the same bucketed by (dx mod G, dy mod G), w = index
+  int32_t* pboff = nullptr;     // [G*G+1]   first bucketed segment of each bucket
+  int32_t* rowoff = nullptr;    // [ngroup][npos+1] reaction entries of a dense group before
+                                //           each positive segment; [npos] = total
+  int32_t* gipre = nullptr;     // [ngroup][G*G] particles of a group before each of its z-runs
+  int32_t* gntot = nullptr;     // [ngroup]  particles per i-group
+  long long* gtot = nullptr;    // [ngroup]  reaction partials per i-group
+  long long* gbase = nullptr;   // [ngroup+1] exclusive scan of gtot; [ngroup] = total
+  long long* gscan_tmp = nullptr;  // tile sums of that scan
+  void* rpart = nullptr;        // [3][rcap] reaction partials (T), SoA
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
   void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
@@ -82,6 +112,8 @@ struct p3m_plan {
   int ngd = 0;                  // i-groups per side
   int64_t ngroup = 0;
   int nrows = 0;
+  int nseg = 0, npos = 0;       // stencil segments, and the positive ones
+  int64_t rcap = 0;             // reaction partials the plan holds (0: two-sided sum only)
   int64_t max_items = 0;
   int tab_var = 0;              // FP32 split table: variable (0: r, 1: softened r)
   double tab_v0 = 0, tab_v1 = 0;  // and its range, as lengths
@@ -126,6 +158,15 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
                         bool uniform_mass, void* acc_out = nullptr);
 template <typename T>
 hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
+// One-sided pair sum: per-group half-stencil offsets and partial bases
+// (before the pair kernel), and the gather of the reaction partials onto the
+// sorted action in ws.acc_pm (after it): the result goes to acc_out (sorted,
+// T4) if not null, else to out in input order as m * a (float if out_fp32).
+hipError_t launch_react_prepass(p3m_plan* P);
+int64_t react_scan_tmp_size(int64_t ngroup);
+template <typename T>
+hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool uniform_mass,
+                               void* acc_out, void* out, int out_fp32);
 template <typename T>
 hipError_t launch_tables(p3m_plan* P);
 
@@ -160,6 +201,12 @@ hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double*
 
 // Host geometry helpers.
 int stencil_rows(int g, double radius_cells, int32_t* out, int cap);
+// The stencil rows cut where their z range crosses a group boundary: each
+// segment lies in one group at offset (ox, oy, oz) = floor((dx, dy, dz) / g),
+// with the sign of that offset in lexicographic order (0: the group itself).
+// Entries (dx & 0xffff | dy << 16, dz_lo, dz_hi, sign); returns the count
+// (and the positive count in *npos).
+int segment_rows(int g, double radius_cells, int32_t* out, int cap, int* npos);
 // Validation of the parameters (the checks and status codes of
 // p3m_plan_create) and the plan's geometry: grid, split and cutoff lengths,
 // i-group edge, stencil row count, work-list bound. Allocates nothing.

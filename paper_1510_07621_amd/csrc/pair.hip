@@ -107,6 +107,17 @@ struct PairArgs {
   void* __restrict__ force;
   int force_fp32;
   unsigned long long* __restrict__ counter;      // pair count mode
+  // one-sided sum between dense groups: the stencil's group segments,
+  // particles per group, per-group reaction offsets and partial bases, the
+  // partials [3][rcap] and their total this call (gbase[ngroup])
+  const int4* __restrict__ segrows;
+  int nseg, npos;
+  const int32_t* __restrict__ gntot;
+  const int32_t* __restrict__ rowoff;
+  const long long* __restrict__ gbase;
+  const long long* __restrict__ gtotal;
+  void* __restrict__ rpart;
+  long long rcap;
 };
 
 // The split-factor table in LDS, one array per coefficient so that the
@@ -345,7 +356,21 @@ __device__ __forceinline__ int wave_inclusive(int v) {
   return v;
 }
 
-template <typename T, bool VJP>
+// The bounding box of an item's i-particles (relative to the group's first
+// cell, in the kernel's position units) and the reach r_c (with a 1e-4
+// margin, far above rounding): a stencil cell whose box stays farther than
+// r_c from the item's box holds no partner of any of its particles, so the
+// rows are clipped to the cells within reach.
+template <typename T>
+struct ItemBox {
+  T lo[3], hi[3];
+  T hs;       // cell size
+  T reach2;   // (r_c (1 + 1e-4))^2
+};
+template <>
+struct ItemBox<double> {};     // the FP64 pair loop stages whole rows
+
+template <typename T, bool VJP, bool HALF>
 struct PairShared {
   SplitTable<T> tab;                       // first, so one address register reaches
                                            // all coefficient arrays
@@ -353,10 +378,57 @@ struct PairShared {
                                                 // the reduction
   typename Vec<T>::v4 jl[VJP ? Stage<T, VJP>::kCap + kStreams : 1];   // adjoint mode: staged j cotangents
   int d_lo[kDesc], d_pre[kDesc + 1], d_zs[kDesc];
+  int d_rp[HALF ? kDesc : 1];              // one-sided sum: partial offset of each run's
+                                           // first entry in the item's reactions, or -1
   int owner[Stage<T, VJP>::kCap];               // run of each staged entry of a chunk
   int d_rx[64], d_ry[64];                  // x, y cell offsets of each row
   int i_lo[16], i_pre[17];
+  ItemBox<T> box;                          // the item's i-particles' bounding box
 };
+
+// Sum of v over each aligned group of nu lanes (nu a power of two <= 32),
+// left in the group's top lane (lane % nu == nu - 1): pairwise sums inside
+// quads, then right shifts within rows of 16, then the row broadcast. The
+// other lanes hold partial sums.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_take(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_take(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int NU, typename T>
+__device__ __forceinline__ T group_sum_top(T v) {
+  if constexpr (NU >= 2) v += dpp_take<0xB1>(v);          // quad_perm [1, 0, 3, 2]
+  if constexpr (NU >= 4) v += dpp_take<0x4E>(v);          // quad_perm [2, 3, 0, 1]
+  if constexpr (NU >= 8) v += dpp_take<0x114>(v);         // row_shr:4
+  if constexpr (NU >= 16) v += dpp_take<0x118>(v);        // row_shr:8
+  if constexpr (NU >= 32) v += dpp_take<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
+// Cells [z0, z1] of the column at (dx, dy) clipped to those within reach of
+// the item's box; false if none.
+template <typename T>
+__device__ __forceinline__ bool clip_to_box(const ItemBox<T>& B, int dx, int dy, int& z0,
+                                            int& z1) {
+  if constexpr (sizeof(T) == 8) {
+    return true;     // FP64: whole rows
+  } else {
+  const T gx = fmax(T(0), fmax(T(dx) * B.hs - B.hi[0], B.lo[0] - T(dx + 1) * B.hs));
+  const T gy = fmax(T(0), fmax(T(dy) * B.hs - B.hi[1], B.lo[1] - T(dy + 1) * B.hs));
+  const T rem = B.reach2 - gx * gx - gy * gy;
+  if (!(rem > T(0))) return false;
+  const T zr = sqrt(rem);
+  z0 = max(z0, (int)floor((B.lo[2] - zr) / B.hs));
+  z1 = min(z1, (int)floor((B.hi[2] + zr) / B.hs));
+  return z0 <= z1;
+  }
+}
 
 // One stencil row (per lane) resolved into at most three contiguous sorted
 // runs (the z-run split where it crosses the periodic box face): first slot,
@@ -365,23 +437,31 @@ template <typename T>
 struct RowRuns {
   int cnt[3], lo[3], zs[3];
   int rx, ry;                               // x, y cell offset of the row's column
+  int rf;                                   // one-sided sum: run 0 takes reactions
 };
 
 template <typename T>
-__device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, int rb, int lane,
-                                                   int gx0, int gy0, int gz0) {
+__device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, const int4* rows,
+                                                   int nrows, int rb, int lane, int gx0,
+                                                   int gy0, int gz0, const ItemBox<T>& B) {
   RowRuns<T> R;
   const int lg = A.lg, ng = A.ng, mask = ng - 1;
 #pragma unroll
   for (int k = 0; k < 3; ++k) R.cnt[k] = R.lo[k] = R.zs[k] = 0;
-  R.rx = R.ry = 0;
-  if (rb + lane < A.nrows) {
-    const int4 row = A.rows[rb + lane];
+  R.rx = R.ry = R.rf = 0;
+  int z0 = 0, z1 = -1;
+  int4 row = make_int4(0, 0, 0, -1);
+  if (rb + lane < nrows) {
+    row = rows[rb + lane];
+    z0 = row.z;
+    z1 = row.w;
+  }
+  if (z0 <= z1 && clip_to_box(B, row.x, row.y, z0, z1)) {
     const int jx = (gx0 + row.x) & mask, jy = (gy0 + row.y) & mask;
     R.rx = row.x;
     R.ry = row.y;
-    const int zhi = gz0 + row.w;
-    int z = gz0 + row.z;
+    const int zhi = gz0 + z1;
+    int z = gz0 + z0;
     const int cbase = ((jx << lg) | jy) << lg;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -399,12 +479,83 @@ __device__ __forceinline__ RowRuns<T> resolve_rows(const PairArgs<T>& A, int rb,
   return R;
 }
 
+// The item's own group as runs (one z-run of G cells per lane < G^2, in the
+// group's flattened order), from flattened index `from` on.
+template <typename T, typename SH>
+__device__ __forceinline__ RowRuns<T> own_group_runs(const SH& S, int lane,
+                                                     int lgG, int G, int gz0, int from) {
+  RowRuns<T> R;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) R.cnt[k] = R.lo[k] = R.zs[k] = 0;
+  R.rx = R.ry = R.rf = 0;
+  if (lane < G * G) {
+    const int c = S.i_pre[lane + 1] - S.i_pre[lane];
+    const int skip = min(max(from - S.i_pre[lane], 0), c);
+    R.rx = lane >> lgG;
+    R.ry = lane & (G - 1);
+    R.lo[0] = S.i_lo[lane] + skip;
+    R.cnt[0] = c - skip;
+    R.zs[0] = -gz0;
+  }
+  return R;
+}
+
+// One group segment of the stencil (per lane) for an item of a dense group:
+// a segment in another dense group at a positive offset is staged with its
+// reactions, one in a sparse group (either sign) without, others not at
+// all (the group's own segments: staged from the group itself; a dense
+// group at a negative offset: that group evaluates the pairs). A segment
+// lies inside one group, so it is one contiguous run.
+template <typename T>
+__device__ __forceinline__ RowRuns<T> resolve_segments(const PairArgs<T>& A, int rb, int lane,
+                                                       int gx0, int gy0, int gz0,
+                                                       const ItemBox<T>& B) {
+  RowRuns<T> R;
+  const int lg = A.lg, ng = A.ng, mask = ng - 1, lgG = A.lgG;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) R.cnt[k] = R.lo[k] = R.zs[k] = 0;
+  R.rx = R.ry = R.rf = 0;
+  if (rb + lane < A.nseg) {
+    const int4 sg = A.segrows[rb + lane];
+    const int dx = (int)(short)(sg.x & 0xffff), dy = sg.x >> 16;
+    const int lgd = lg - lgG, md = (1 << lgd) - 1;
+    const int64_t g2 = ((int64_t)(((gx0 >> lgG) + (dx >> lgG)) & md) << (2 * lgd)) |
+                       ((int64_t)(((gy0 >> lgG) + (dy >> lgG)) & md) << lgd) |
+                       (((gz0 >> lgG) + (sg.y >> lgG)) & md);
+    const bool dense = sg.w != 0 && A.gntot[g2] > kDenseMin;
+    const bool react = sg.w > 0 && dense;
+    // a segment without reactions is clipped to the cells within reach of
+    // the item's box; one with reactions is staged whole (the partial
+    // offsets of all the group's items follow its full particle count)
+    int z0 = sg.y, z1 = sg.z;
+    if ((sg.w > 0 || (sg.w < 0 && !dense)) && (react || clip_to_box(B, dx, dy, z0, z1))) {
+      const int jx = (gx0 + dx) & mask, jy = (gy0 + dy) & mask;
+      const int cbase = ((jx << lg) | jy) << lg;
+      const int z = gz0 + z0, zw = z & mask;
+      const int l0 = A.start[cbase + zw];
+      R.lo[0] = l0;
+      R.cnt[0] = A.start[cbase + zw + (z1 - z0 + 1)] - l0;
+      R.zs[0] = (z - zw) - gz0;
+      R.rx = dx;
+      R.ry = dy;
+      R.rf = react;
+    }
+  }
+  return R;
+}
+
 // One work item with U i-slots per lane. UM: every particle has the same mass
 // (mass applied once at the end instead of per pair). VJP: the adjoint sum
-// J(r_ij) (lam_i - lam_j) in place of the force r_ij g(r_ij).
-template <typename T, int U, bool COUNT, bool UM, int TAB, bool VJP>
-__device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJP>& S, int gx0,
-                                          int gy0, int gz0, int ibeg, int ni) {
+// J(r_ij) (lam_i - lam_j) in place of the force r_ij g(r_ij). HALF: the
+// one-sided sum (each pair of distinct items' particles once, the reaction
+// on every staged entry past the item's own chunk written as a partial);
+// else every pair from both sides over the full stencil. NU: the number of
+// slot sets of the one-sided sum (a power of two, fixed per instantiation so
+// that the sums over them are straight-line code).
+template <typename T, int U, bool COUNT, bool UM, int TAB, bool VJP, bool HALF, int NU,
+          typename SH>
+__device__ __forceinline__ void pair_item(const PairArgs<T>& A, SH& S, int gx0,
+                                          int gy0, int gz0, int ibeg, int ni, int64_t g) {
   using T4 = typename Vec<T>::v4;
   constexpr int kCap = Stage<T, VJP>::kCap, kStage = Stage<T, VJP>::kPer;
   const int lane = threadIdx.x;
@@ -421,13 +572,16 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
     const T v = fma(T(cell), h, off);
     return SC ? v * ps : v;
   };
-  const int nu = (ni + U - 1) / U;      // slot sets
+  // slot sets; the one-sided sum sums each staged entry's reaction over the
+  // sets, so their number is rounded up to a power of two (empty sets idle)
+  const int nu = HALF ? NU : (ni + U - 1) / U;
   const int ns = min(64 / nu, kStreams);  // streams
   const int il = lane % nu, st = lane / nu;
   const bool active = st < ns;
 
   T xi[U], yi[U], zi[U], ax[U], ay[U], az[U];
   T lxi[VJP ? U : 1], lyi[VJP ? U : 1], lzi[VJP ? U : 1];
+  T mi[HALF && !UM ? U : 1];
   int si[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -443,6 +597,7 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
     yi[u] = has ? coord(run & (G - 1), pi.y) : T(kFar);
     zi[u] = has ? coord(czi - gz0, pi.z) : T(kFar);
     ax[u] = ay[u] = az[u] = T(0);
+    if constexpr (HALF && !UM) mi[u] = pi.w;
     if constexpr (VJP) {
       const T4 li = A.lam[si[u]];
       lxi[u] = li.x;
@@ -450,15 +605,68 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
       lzi[u] = li.z;
     }
   }
-  int npairs = 0;
+  // the item's bounding box (empty slots excluded), for clipping the rows;
+  // kept in LDS (read once per batch of rows) to spare registers. FP32
+  // only: the FP64 pair loop measured slower with it (117 -> 125 ms on the
+  // 256^3 clustered set; FP32 44.3 -> 41.8 ms).
+  if constexpr (sizeof(T) == 4) {
+    T lo0 = T(kFar), lo1 = T(kFar), lo2 = T(kFar), hi0 = T(-kFar), hi1 = T(-kFar), hi2 = T(-kFar);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (xi[u] < T(0.5 * kFar)) {        // a particle, not an empty slot
+        lo0 = fmin(lo0, xi[u]); hi0 = fmax(hi0, xi[u]);
+        lo1 = fmin(lo1, yi[u]); hi1 = fmax(hi1, yi[u]);
+        lo2 = fmin(lo2, zi[u]); hi2 = fmax(hi2, zi[u]);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo0 = fmin(lo0, __shfl_xor(lo0, o, 64)); hi0 = fmax(hi0, __shfl_xor(hi0, o, 64));
+      lo1 = fmin(lo1, __shfl_xor(lo1, o, 64)); hi1 = fmax(hi1, __shfl_xor(hi1, o, 64));
+      lo2 = fmin(lo2, __shfl_xor(lo2, o, 64)); hi2 = fmax(hi2, __shfl_xor(hi2, o, 64));
+    }
+    if (lane == 0) {
+      S.box.lo[0] = lo0; S.box.lo[1] = lo1; S.box.lo[2] = lo2;
+      S.box.hi[0] = hi0; S.box.hi[1] = hi1; S.box.hi[2] = hi2;
+      S.box.hs = SC ? h * ps : h;
+      S.box.reach2 = (SC ? A.rc2s : A.rc2) * T(1.0002);
 
-  // Stencil rows are resolved 64 at a time (one per lane). (Fetching the next
-  // batch's start[] entries ahead measured no faster and costs registers.)
-  for (int rb = 0; rb < A.nrows; rb += 64) {
-    const RowRuns<T> cur = resolve_rows<T>(A, rb, lane, gx0, gy0, gz0);
+    }
+    __syncthreads();
+  }
+  const ItemBox<T>& B = S.box;
+  int npairs = 0;
+  // one-sided sum: the item's partials start at ibase; staged entry P (in
+  // staging order over the item's own group, then the half stencil) past its
+  // own chunk (P >= ni) goes to ibase + P - ni
+  long long ibase = 0, ptotal = 0;
+  int staged = 0;     // entries staged so far (phase 1: the item's own group)
+  int rstaged = 0;    // reaction entries staged so far (phase 2: the segments)
+  if constexpr (HALF) {
+    ptotal = *A.gtotal;
+    const int ntot = S.i_pre[GG];
+    const int L = A.rowoff[g * (A.npos + 1) + A.npos];
+    const int a = ibeg / kChunk;
+    ibase = A.gbase[g] + (long long)a * (ntot + L) - 32LL * a * (a + 1);
+  }
+
+  // The staged entries of one batch of rows (descriptors per lane), kCap at
+  // a time.
+  // phase 1: the item's own group (reactions for entries past its own
+  // chunk, by position); phase 2: group segments (reactions for flagged runs).
+  auto run_batch = [&](const RowRuns<T>& cur, int phase) {
     __syncthreads();       // previous batch is done with the descriptors and jb
     const int tot_l = cur.cnt[0] + cur.cnt[1] + cur.cnt[2];
     const int inc = wave_inclusive(tot_l);
+    int rtotal = 0;
+    if (HALF && phase == 2) {
+      const int rc = cur.rf ? cur.cnt[0] : 0;
+      const int rinc = wave_inclusive(rc);
+      const int intra = S.i_pre[GG] - ibeg - ni;
+      S.d_rp[3 * lane] = cur.rf ? intra + rstaged + rinc - rc : -1;
+      S.d_rp[3 * lane + 1] = S.d_rp[3 * lane + 2] = -1;
+      rtotal = __builtin_amdgcn_readfirstlane(__shfl(rinc, 63, 64));
+    }
     int pre[3];
     {
       int base = inc - tot_l;
@@ -555,17 +763,22 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
       // count is wave-uniform; reads past the end (at most ns - 1) hit the
       // sentinels, and empty slots sit at +kFar, so both fail the cutoff test.
       // Lanes beyond the streams (st >= ns, all slots empty) read stream 0's
-      // entries, so no read passes the sentinels.
+      // entries, so no read passes the sentinels. In the one-sided sum the
+      // top lane of each stream's slot sets writes the step's reaction on its
+      // entry over that entry in jb once every lane has read it (each entry
+      // is read in one step only, by its own stream).
       const int iters = (cn + ns - 1) / ns;
       const int st_r = active ? st : 0;
-      const T4* jp = S.jb + st_r;
+      T4* jp = S.jb + st_r;
+      const bool top = active && il == nu - 1;
       if constexpr (VJP) {
         // sentinel slots carry no cotangent; their separations fail the test
         const T4* lp = S.jl + st_r;
 #pragma unroll 2
         for (int t = 0; t < iters; ++t) {
-          const T4& pj = jp[t * ns];
+          const T4 pj = jp[t * ns];
           const T4 lj = t * ns + st_r < cn ? lp[t * ns] : T4{};
+          T rx = 0, ry = 0, rz = 0;
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const T dx = xi[u] - pj.x, dy = yi[u] - pj.y, dz = zi[u] - pj.z;
@@ -574,69 +787,146 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
               T w1, w2;
               pair_vjp_weights<TAB>(r2, A, S.tab, w1, w2);
               const T lx = lxi[u] - lj.x, ly = lyi[u] - lj.y, lz = lzi[u] - lj.z;
-              T c = w2 * (dx * lx + dy * ly + dz * lz);
-              if (!UM) {
-                w1 *= pj.w;
-                c *= pj.w;
+              const T c = w2 * (dx * lx + dy * ly + dz * lz);
+              const T tx = w1 * lx + c * dx, ty = w1 * ly + c * dy, tz = w1 * lz + c * dz;
+              if constexpr (UM) {
+                ax[u] += tx;
+                ay[u] += ty;
+                az[u] += tz;
+                if constexpr (HALF) {
+                  rx += tx;
+                  ry += ty;
+                  rz += tz;
+                }
+              } else {
+                ax[u] += pj.w * tx;
+                ay[u] += pj.w * ty;
+                az[u] += pj.w * tz;
+                if constexpr (HALF) {
+                  rx += mi[u] * tx;
+                  ry += mi[u] * ty;
+                  rz += mi[u] * tz;
+                }
               }
-              ax[u] += w1 * lx + c * dx;
-              ay[u] += w1 * ly + c * dy;
-              az[u] += w1 * lz + c * dz;
+            }
+          }
+          if constexpr (HALF) {
+            rx = group_sum_top<NU>(rx);
+            ry = group_sum_top<NU>(ry);
+            rz = group_sum_top<NU>(rz);
+            if (top) {
+              T4 o;
+              o.x = rx; o.y = ry; o.z = rz; o.w = T(0);
+              jp[t * ns] = o;
             }
           }
         }
-        continue;
-      }
-      // RHO (force over the softened-distance table): the squared separation
-      // is accumulated on top of eps^2, so the test compares
-      // rho^2 = r^2 + eps^2 with r_c^2 + eps^2 and the weight starts from rho^2
-      // (FP32: all of it in the scaled units)
-      constexpr bool RHO = TAB == 1 && !COUNT;
-      const T e2r = sizeof(T) == 4 ? T(A.rho_e2) : T(A.rho_e2d);
-      const T cut2 = RHO ? (sizeof(T) == 4 ? T(A.rho_cut2) : T(A.rho_cut2d)) : A.rc2;
-      // FP64 reads the next staged j while the current one is tested
-      // (measured 3 % faster; FP32 gains nothing and spills more)
-      constexpr bool PF = sizeof(T) == 8;
-      T4 pn = jp[0];
+      } else {
+        // RHO (force over the softened-distance table): the squared separation
+        // is accumulated on top of eps^2, so the test compares
+        // rho^2 = r^2 + eps^2 with r_c^2 + eps^2 and the weight starts from rho^2
+        // (FP32: all of it in the scaled units)
+        constexpr bool RHO = TAB == 1 && !COUNT;
+        const T e2r = sizeof(T) == 4 ? T(A.rho_e2) : T(A.rho_e2d);
+        const T cut2 = RHO ? (sizeof(T) == 4 ? T(A.rho_cut2) : T(A.rho_cut2d)) : A.rc2;
+        // FP64 reads the next staged j while the current one is tested
+        // (measured 3 % faster; FP32 gains nothing and spills more)
+        constexpr bool PF = sizeof(T) == 8;
+        T4 pn = jp[0];
 #pragma unroll 2
-      for (int t = 0; t < iters; ++t) {
-        T4 pj;
-        if constexpr (PF) {
-          pj = pn;
-          pn = jp[min(t + 1, iters - 1) * ns];
-        } else {
-          pj = jp[t * ns];
-        }
-        const T jx = pj.x, jy = pj.y, jz = pj.z;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const T dx = xi[u] - jx, dy = yi[u] - jy, dz = zi[u] - jz;
-          T r2;
-          if constexpr (RHO) {
-            r2 = fma(dx, dx, e2r);
-            r2 = fma(dy, dy, r2);
-            r2 = fma(dz, dz, r2);
+        for (int t = 0; t < iters; ++t) {
+          T4 pj;
+          if constexpr (PF) {
+            pj = pn;
+            pn = jp[min(t + 1, iters - 1) * ns];
           } else {
-            r2 = dx * dx + dy * dy + dz * dz;
+            pj = jp[t * ns];
           }
-          if (r2 < cut2) {
-            if (COUNT) {
-              npairs += r2 > T(0) ? 1 : 0;
+          const T jx = pj.x, jy = pj.y, jz = pj.z;
+          T rx = 0, ry = 0, rz = 0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const T dx = xi[u] - jx, dy = yi[u] - jy, dz = zi[u] - jz;
+            T r2;
+            if constexpr (RHO) {
+              r2 = fma(dx, dx, e2r);
+              r2 = fma(dy, dy, r2);
+              r2 = fma(dz, dz, r2);
             } else {
-              T w;
-              if constexpr (RHO)
-                w = pair_weight_rho(r2, A, S.tab);
-              else
-                w = pair_weight<TAB>(r2, A, S.tab);
-              if (!UM) w *= pj.w;
-              ax[u] += w * dx;
-              ay[u] += w * dy;
-              az[u] += w * dz;
+              r2 = dx * dx + dy * dy + dz * dz;
             }
+            if (r2 < cut2) {
+              if (COUNT) {
+                npairs += r2 > T(0) ? 1 : 0;
+              } else {
+                T w;
+                if constexpr (RHO)
+                  w = pair_weight_rho(r2, A, S.tab);
+                else
+                  w = pair_weight<TAB>(r2, A, S.tab);
+                const T wa = UM ? w : w * pj.w;
+                ax[u] += wa * dx;
+                ay[u] += wa * dy;
+                az[u] += wa * dz;
+                if constexpr (HALF) {
+                  const T wr = UM ? w : w * mi[u];
+                  rx += wr * dx;
+                  ry += wr * dy;
+                  rz += wr * dz;
+                }
+              }
+            }
+          }
+          if constexpr (HALF) {
+            rx = group_sum_top<NU>(rx);
+            ry = group_sum_top<NU>(ry);
+            rz = group_sum_top<NU>(rz);
+            if (top) {
+              T4 o;
+              o.x = rx; o.y = ry; o.z = rz; o.w = T(0);
+              jp[t * ns] = o;
+            }
+          }
+        }
+      }
+      if constexpr (HALF) {
+        // the chunk's reactions to their partials: each lane its own staged
+        // entries (phase 1: those past the item's own chunk, at their
+        // position; phase 2: those of runs that take reactions)
+        __syncthreads();
+        T* px = (T*)A.rpart;
+#pragma unroll
+        for (int e = 0; e < kStage; ++e) {
+          const int q = q0 + e;
+          if (q >= cn) continue;
+          long long idx = -1;
+          if (phase == 1) {
+            const int P = staged + c0 + q;
+            if (P >= ni) idx = ibase + (P - ni);
+          } else {
+            const int rp = S.d_rp[dd[e]];
+            if (rp >= 0) idx = ibase + rp + (c0 + q - S.d_pre[dd[e]]);
+          }
+          if (idx >= 0 && idx < ptotal) {    // (always below: a guard only)
+            const T4 r = S.jb[q];
+            px[idx] = r.x;
+            px[A.rcap + idx] = r.y;
+            px[2 * A.rcap + idx] = r.z;
           }
         }
       }
     }
+    staged += total;
+    rstaged += rtotal;
+  };
+
+  if constexpr (HALF) {
+    run_batch(own_group_runs<T>(S, lane, lgG, G, gz0, ibeg), 1);
+    for (int rb = 0; rb < A.nseg; rb += 64)
+      run_batch(resolve_segments<T>(A, rb, lane, gx0, gy0, gz0, B), 2);
+  } else {
+    for (int rb = 0; rb < A.nrows; rb += 64)
+      run_batch(resolve_rows<T>(A, A.rows, A.nrows, rb, lane, gx0, gy0, gz0, B), 0);
   }
 
   if (COUNT) {
@@ -702,10 +992,57 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, PairShared<T, VJ
   }
 }
 
-template <typename T, bool COUNT, bool UM, int TAB, bool VJP = false>
+// i-slots per lane: enough that ceil(ni / U) slot sets fit in the wave. The
+// one-sided sum rounds the slot sets up to a power of two NU.
+template <typename T, bool COUNT, bool UM, int TAB, bool VJP, bool HALF, typename SH>
+__device__ __forceinline__ void pair_dispatch(const PairArgs<T>& A, SH& S,
+                                              int gx0, int gy0, int gz0, int ibeg, int ni,
+                                              int64_t g) {
+#define P3M_ITEM(U_, NU_) \
+  pair_item<T, U_, COUNT, UM, TAB, VJP, HALF, NU_>(A, S, gx0, gy0, gz0, ibeg, ni, g)
+  if constexpr (!HALF) {
+    if (ni == 1)
+      P3M_ITEM(1, 0);
+    else if (sizeof(T) == 8)
+      P3M_ITEM(2, 0);
+    else if (ni <= 32 || VJP)
+      P3M_ITEM(4, 0);
+    else
+      P3M_ITEM(8, 0);
+  } else if constexpr (sizeof(T) == 8) {
+    if (ni == 1)
+      P3M_ITEM(1, 1);
+    else if (ni <= 4)
+      P3M_ITEM(2, 2);
+    else if (ni <= 8)
+      P3M_ITEM(2, 4);
+    else if (ni <= 16)
+      P3M_ITEM(2, 8);
+    else if (ni <= 32)
+      P3M_ITEM(2, 16);
+    else
+      P3M_ITEM(2, 32);
+  } else {
+    if (ni == 1)
+      P3M_ITEM(1, 1);
+    else if (ni <= 8)
+      P3M_ITEM(4, 2);
+    else if (ni <= 16)
+      P3M_ITEM(4, 4);
+    else if (ni <= 32)
+      P3M_ITEM(4, 8);
+    else if constexpr (!VJP)
+      P3M_ITEM(8, 8);
+    else
+      P3M_ITEM(4, 16);
+  }
+#undef P3M_ITEM
+}
+
+template <typename T, bool COUNT, bool UM, int TAB, bool VJP = false, bool HALF = false>
 __global__ void __launch_bounds__(64, (kPairWaves<T, VJP>))
 k_pairs(PairArgs<T> A) {
-  __shared__ PairShared<T, VJP> S;
+  __shared__ PairShared<T, VJP, HALF> S;
   const int lane = threadIdx.x;
   // Items in group order, dealt round-robin over the XCDs by the hardware:
   // the eight XCDs then work on neighbouring groups at the same time, which
@@ -742,15 +1079,13 @@ k_pairs(PairArgs<T> A) {
   const int ntot = __builtin_amdgcn_readfirstlane(S.i_pre[GG]);
   const int ibeg = it.y * kChunk;
   const int ni = min(kChunk, ntot - ibeg);
-  // i-slots per lane: enough that ceil(ni / U) slot sets fit in the wave
-  if (ni == 1)
-    pair_item<T, 1, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
-  else if (sizeof(T) == 8)
-    pair_item<T, 2, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
-  else if (ni <= 32 || VJP)
-    pair_item<T, 4, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
+  // the one-sided sum for an item of a dense group, unless the partials
+  // exceed the plan's capacity this call (then every pair from both sides,
+  // as in a plan without partials); items of sparse groups from both sides
+  if (HALF && ntot > kDenseMin && *A.gtotal <= A.rcap)
+    pair_dispatch<T, COUNT, UM, TAB, VJP, true>(A, S, gx0, gy0, gz0, ibeg, ni, it.x);
   else
-    pair_item<T, 8, COUNT, UM, TAB, VJP>(A, S, gx0, gy0, gz0, ibeg, ni);
+    pair_dispatch<T, COUNT, UM, TAB, VJP, false>(A, S, gx0, gy0, gz0, ibeg, ni, it.x);
 }
 
 // Grid of the pair kernel: the item bound rounded up to a multiple of kXcds.
@@ -816,56 +1151,101 @@ PairArgs<T> make_args(p3m_plan* P, int64_t n) {
   A.vjp_ce_s = (T)(ce / (s_tab * s_tab * s_tab));
   A.perm = W.perm;
   A.n = n;
+  A.segrows = W.segrows;
+  A.nseg = P->nseg;
+  A.npos = P->npos;
+  A.gntot = W.gntot;
+  A.rowoff = W.rowoff;
+  A.gbase = W.gbase;
+  A.gtotal = W.gbase ? W.gbase + P->ngroup : nullptr;
+  A.rpart = W.rpart;
+  A.rcap = P->rcap;
   return A;
 }
 
+// Scale of the pair kernel's sorted output (times the mass when all masses
+// are equal): the reaction partials enter the gather with its negative.
+template <typename T>
+double out_scale(const PairArgs<T>& A, int tab, bool vjp) {
+  return tab != 1 ? A.wscale : (vjp ? A.wscale_vjp : A.wscale_rho);
+}
+
 }  // namespace
+
+template <typename T, bool VJP>
+hipError_t launch_pair_kernel(p3m_plan* P, const PairArgs<T>& A, bool uniform_mass, bool half) {
+  const unsigned grid = pair_grid(P);
+  const bool tab = (sizeof(T) == 4 ? P->tab_var : P->tab64_var) == 1;
+  // table over the softened distance (1) or over r (0)
+  if (half) {
+    if (tab) {
+      if (uniform_mass)
+        k_pairs<T, false, true, 1, VJP, true><<<grid, 64, 0, P->stream>>>(A);
+      else
+        k_pairs<T, false, false, 1, VJP, true><<<grid, 64, 0, P->stream>>>(A);
+    } else {
+      if (uniform_mass)
+        k_pairs<T, false, true, 0, VJP, true><<<grid, 64, 0, P->stream>>>(A);
+      else
+        k_pairs<T, false, false, 0, VJP, true><<<grid, 64, 0, P->stream>>>(A);
+    }
+    return hipGetLastError();
+  }
+  if (tab) {
+    if (uniform_mass)
+      k_pairs<T, false, true, 1, VJP><<<grid, 64, 0, P->stream>>>(A);
+    else
+      k_pairs<T, false, false, 1, VJP><<<grid, 64, 0, P->stream>>>(A);
+  } else {
+    if (uniform_mass)
+      k_pairs<T, false, true, 0, VJP><<<grid, 64, 0, P->stream>>>(A);
+    else
+      k_pairs<T, false, false, 0, VJP><<<grid, 64, 0, P->stream>>>(A);
+  }
+  return hipGetLastError();
+}
+
+// The one-sided sum: offsets and partial bases, the pair kernel (sorted
+// action into ws.acc_pm), the gather (acc_out sorted, or out in input order).
+template <typename T, bool VJP>
+hipError_t launch_half(p3m_plan* P, int64_t n, PairArgs<T> A, bool uniform_mass,
+                       void* acc_out, void* out, int out_fp32) {
+  hipError_t e = launch_react_prepass(P);
+  if (e != hipSuccess) return e;
+  A.acc_pm = nullptr;
+  A.acc_out = (typename Vec<T>::v4*)P->ws.acc_pm;
+  A.force = nullptr;
+  if ((e = launch_pair_kernel<T, VJP>(P, A, uniform_mass, true)) != hipSuccess) return e;
+  const int tab = sizeof(T) == 4 ? P->tab_var : P->tab64_var;
+  return launch_react_gather<T>(P, n, -out_scale(A, tab, VJP), uniform_mass, acc_out, out,
+                                out_fp32);
+}
 
 template <typename T>
 hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32,
                         bool uniform_mass, void* acc_out) {
   PairArgs<T> A = make_args<T>(P, n);
+  if (P->rcap > 0 && !add_pm)
+    return launch_half<T, false>(P, n, A, uniform_mass, acc_out, force_out, force_fp32);
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
   A.acc_out = (typename Vec<T>::v4*)acc_out;
   A.force = force_out;
   A.force_fp32 = force_fp32;
-  const unsigned grid = pair_grid(P);
-  if ((sizeof(T) == 4 ? P->tab_var : P->tab64_var) == 1) {   // table over the softened distance
-    if (uniform_mass)
-      k_pairs<T, false, true, 1><<<grid, 64, 0, P->stream>>>(A);
-    else
-      k_pairs<T, false, false, 1><<<grid, 64, 0, P->stream>>>(A);
-    return hipGetLastError();
-  }
-  if (uniform_mass)
-    k_pairs<T, false, true, 0><<<grid, 64, 0, P->stream>>>(A);
-  else
-    k_pairs<T, false, false, 0><<<grid, 64, 0, P->stream>>>(A);
-  return hipGetLastError();
+  return launch_pair_kernel<T, false>(P, A, uniform_mass, false);
 }
 
 template <typename T>
 hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar,
                             bool uniform_mass, void* acc_out) {
   PairArgs<T> A = make_args<T>(P, n);
+  A.lam = (const typename Vec<T>::v4*)P->ws.lam;
+  if (P->rcap > 0 && !add_pm)
+    return launch_half<T, true>(P, n, A, uniform_mass, acc_out, pos_bar, 0);
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
   A.acc_out = (typename Vec<T>::v4*)acc_out;
-  A.lam = (const typename Vec<T>::v4*)P->ws.lam;
   A.force = pos_bar;
   A.force_fp32 = 0;
-  const unsigned grid = pair_grid(P);
-  if ((sizeof(T) == 4 ? P->tab_var : P->tab64_var) == 1) {
-    if (uniform_mass)
-      k_pairs<T, false, true, 1, true><<<grid, 64, 0, P->stream>>>(A);
-    else
-      k_pairs<T, false, false, 1, true><<<grid, 64, 0, P->stream>>>(A);
-    return hipGetLastError();
-  }
-  if (uniform_mass)
-    k_pairs<T, false, true, 0, true><<<grid, 64, 0, P->stream>>>(A);
-  else
-    k_pairs<T, false, false, 0, true><<<grid, 64, 0, P->stream>>>(A);
-  return hipGetLastError();
+  return launch_pair_kernel<T, true>(P, A, uniform_mass, false);
 }
 
 template <typename T>

@@ -186,6 +186,46 @@ def test_stencil_contains_every_partner_cell_of_random_pairs(b):
         assert tuple(c) in cells
 
 
+@pytest.mark.parametrize("g,R", [(1, 5.625), (2, 5.625), (4, 5.625), (4, 10.0), (2, 1.0)])
+def test_segments_cut_the_stencil_at_groups_and_sign_each_pair_once(b, g, R):
+    """The segments partition the full stencil's cells, each lies in one
+    group and carries the lexicographic sign of that group's offset; of two
+    different groups that hold a pair of cells closer than R cells, exactly
+    one sees the other at a positive offset (so a pair between two groups is
+    evaluated once); the group itself has sign 0. Checked for all cell
+    pairs with the first cell in the group at the origin."""
+    full = b.stencil_rows(g, R)
+    segs = b.segment_rows(g, R)
+    fcells = {(dx, dy, dz) for dx, dy, lo, hi in full for dz in range(lo, hi + 1)}
+    sign = {}
+    for dx, dy, lo, hi, sg in segs:
+        assert lo <= hi and lo // g == hi // g                 # inside one group
+        o = (dx // g, dy // g, lo // g)
+        want = 0 if o == (0, 0, 0) else (1 if o > (0, 0, 0) else -1)
+        assert sg == want
+        for dz in range(lo, hi + 1):
+            assert (dx, dy, dz) not in sign
+            sign[(dx, dy, dz)] = sg
+    assert set(sign) == fcells
+    # order: the full stencil's row order, pieces by increasing z
+    key = {(dx, dy): k for k, (dx, dy, lo, hi) in enumerate(full)}
+    order = [(key[(dx, dy)], lo) for dx, dy, lo, hi, sg in segs]
+    assert order == sorted(order)
+    for ci in itertools.product(range(g), repeat=3):   # i's cell inside the group at 0
+        for cj in fcells:
+            d = tuple(cj[a] - ci[a] for a in range(3))
+            if sum(_gap(x, 1) ** 2 for x in d) >= (R + 1e-9) ** 2:
+                continue                               # no pair of points closer than R
+            o = tuple(cj[a] // g for a in range(3))     # j's group offset
+            if o == (0, 0, 0):
+                assert sign[cj] == 0
+                continue
+            back = tuple(ci[a] - g * o[a] for a in range(3))   # i's cell seen from j's group
+            assert back in sign
+            assert (sign[cj] > 0) != (sign[back] > 0), (ci, cj)
+            assert sign[cj] == -sign[back]
+
+
 def test_group_edge(b):
     assert b.group_edge(128 ** 3, 128) == 4        # one particle per cell -> 64 per group
     assert b.group_edge(16 ** 3, 128) == 4         # sparse: largest group

@@ -71,6 +71,34 @@ def test_force_vjp_parity(case, precision, tol):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_force_vjp_one_sided_on_dense_groups(precision, tol):
+    """The adjoint's pair sum evaluated once per pair between dense groups
+    (pair_partials 80: the cotangent reactions gathered from partials)
+    against the oracle's transpose, on dense cells of 400 and 600 particles
+    in neighbouring groups plus a uniform background, per-particle masses;
+    the scalar-mass path and the full adjoint with the mesh part too."""
+    rng = np.random.default_rng(83)
+    dense = np.concatenate([(np.array([3, 5, 7])[:, None] + rng.random((3, 400))) * H,
+                            (np.array([4, 5, 8])[:, None] + rng.random((3, 600))) * H], axis=1)
+    pos = np.concatenate([dense, ics.uniform(1200, seed=84)], axis=1)
+    n = pos.shape[1]
+    m = rng.uniform(0.5, 1.5, n) / n
+    lam = rng.normal(size=(3, n))
+    eps = 0.03 * H
+    r_s = 1.25 * H
+    ref = adjoint.pp_vjp(pos, m, 1.0, r_s, 4.5 * r_s, eps, lam)
+    ref_s = adjoint.pp_vjp(pos, 1.0 / n, 1.0, r_s, 4.5 * r_s, eps, lam)
+    ref_pm = adjoint.pm_vjp(pos, m, 1.0, GRID, r_s, lam)
+    with plan(GRID, n, precision, softening=eps, adjoint=True, pair_partials=80) as P:
+        got = host(P.pp_force_vjp(dev(pos), dev(m), dev(lam)))
+        got_s = host(P.pp_force_vjp(dev(pos), 1.0 / n, dev(lam)))
+        full = host(P.force_vjp(dev(pos), dev(m), dev(lam)))
+    assert _err(got, ref) <= tol
+    assert _err(got_s, ref_s) <= tol
+    assert _err(full, ref + ref_pm) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
 @pytest.mark.parametrize("soft_cells", [0.0, 0.03])
 def test_coincident_particles_contribute_nothing(precision, tol, soft_cells):
     """Exact duplicates of 60 particles: a pair at zero separation adds

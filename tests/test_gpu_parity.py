@@ -315,6 +315,45 @@ def test_heavy_masses_without_softening_and_duplicates(precision, tol):
     assert e["rms"] <= tol, e
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("pair_partials", [0, 80, 1])
+def test_one_sided_two_sided_and_overflow_fallback(precision, tol, pair_partials):
+    """The short-range sum evaluated from both sides (pair_partials 0), once
+    per pair between dense groups with the reactions gathered from partials
+    (80 per particle), and with a capacity too small for the input (the
+    65536 spare partials only, at 1 per particle, and 4000 more particles
+    in one cell: the call falls back to both sides on the device) all match
+    the oracle: dense cells of 300, 700 and 500 (groups of several chunks,
+    one straddling the z face, two neighbouring), a ragged uniform
+    background, per-particle masses and the scalar mass, in a box whose
+    cell size is not a power of two."""
+    rng = np.random.default_rng(23)
+    grid, box = 16, 2.7
+    h = box / grid
+    cells = [([5, 9, 15], 300), ([5, 9, 0], 700), ([6, 10, 13], 500)]
+    if pair_partials == 1:
+        cells.append(([11, 2, 7], 4000))
+    dense = np.concatenate([(np.array(c)[:, None] + rng.random((3, k))) * h for c, k in cells],
+                           axis=1)
+    pos = np.concatenate([dense, ics.uniform(1701, box, seed=24)], axis=1)
+    n = pos.shape[1]
+    m = rng.uniform(0.5, 1.5, n) / n
+    eps = 0.02 * h
+    r_s = 1.25 * h
+    ref = o_pp.pp_accel(pos, m, box, r_s, 4.5 * r_s, eps, 1.0) * m
+    ref_s = o_pp.pp_accel(pos, 1.0 / n, box, r_s, 4.5 * r_s, eps, 1.0) / n
+    with plan(grid, n, precision, box=box, softening=eps, pair_partials=pair_partials) as P:
+        F = host(P.pp_force(dev(pos), dev(m)))
+        Fs = host(P.pp_force(dev(pos), 1.0 / n))
+        Fp = host(P.force(dev(pos), dev(m)))
+        Fpm = host(P.pm_force(dev(pos), dev(m)))
+    e = _err(F, ref)
+    assert e["rms"] <= tol and e["max"] <= 100 * tol, e
+    e = _err(Fs, ref_s)
+    assert e["rms"] <= tol and e["max"] <= 100 * tol, e
+    assert _err(Fp - Fpm, ref)["rms"] <= 10 * tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_positions_on_faces_and_nodes(precision):
     grid = 32
