@@ -66,5 +66,75 @@ def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libp3m_san.so")
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host code only (the
+# ABI's validation, plan set-up and host helpers); the device code is built
+# as usual.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-g",
+             "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """The shared AddressSanitizer runtime of ROCm's clang (to preload into
+    the process that loads the sanitized library)."""
+    found = sorted(glob.glob(os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..",
+                                          "llvm", "lib", "clang", "*", "lib", "linux",
+                                          "libclang_rt.asan-x86_64.so")))
+    if not found:
+        found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise RuntimeError("libclang_rt.asan-x86_64.so not found")
+    return os.path.realpath(found[-1])
+
+
+def _sources_digest(flags: list[str]) -> str:
+    import hashlib
+    h = hashlib.sha256(" ".join(flags).encode())
+    for pat in (os.path.join(CSRC, "*"), os.path.join(INCLUDE, "*.h")):
+        for p in sorted(glob.glob(pat)):
+            with open(p, "rb") as f:
+                h.update(os.path.basename(p).encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """Build ``_build/san/libp3m_san.so``: the same sources with the host code
+    under ASan + UBSan (host optimisation -O1). Skipped when a build of the
+    same sources and flags is there. Returns the library path."""
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + ["-O1"] + SAN_FLAGS
+    digest = _sources_digest(flags)
+    stamp = os.path.join(SAN_DIR, "sources.sha256")
+    if os.path.exists(SAN_LIB) and os.path.exists(stamp):
+        with open(stamp) as f:
+            if f.read().strip() == digest:
+                return SAN_LIB
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    objs = [os.path.join(SAN_DIR, os.path.basename(s)[:-4] + ".o") for s in srcs]
+
+    def one(src, obj):
+        cmd = [hipcc(), *flags, "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        for f in [ex.submit(one, s, o) for s, o in zip(srcs, objs)]:
+            f.result()
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *SAN_FLAGS[:4],
+           "-shared-libsan", *objs, "-o", SAN_LIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    with open(stamp, "w") as f:
+        f.write(digest + "\n")
+    if verbose:
+        print(f"built {SAN_LIB}")
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True, extra_flags=sys.argv[1:])
