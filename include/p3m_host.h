@@ -110,6 +110,18 @@ int p3m_cosmo_scale_factor(const p3m_cosmology* c, double t, double* a_out);
 int p3m_cosmo_kick_drift(const p3m_cosmology* c, double a0, double a1, double* c_kick,
                          double* c_drift);
 
+/* One kick-drift-kick step in comoving coordinates whose length is a
+ * fraction dt_factor of the age of the universe at its start (guide Ch. 5:
+ * Delta_t_factor; H0, Omega_m, Omega_Lambda and a_begin set the background):
+ * with t0 = t(a) and dt = dt_factor t0, the step ends at a_next = a(t0 + dt);
+ * the first kick covers the first half in time, [a, a(t0 + dt/2)], the
+ * second kick the second half, and the drift the whole step, so a step is
+ *   p += c_kick1 F(x);  x = wrap(x + c_drift p / m);  p += c_kick2 F(x)
+ * with the canonical momenta of p3m_cosmo_kick_drift. Errors as for those
+ * calls; P3M_EINVAL also for dt_factor <= 0 or non-finite, or a null output. */
+int p3m_cosmo_kdk_step(const p3m_cosmology* c, double a, double dt_factor, double* a_next,
+                       double* c_kick1, double* c_drift, double* c_kick2);
+
 #ifdef __cplusplus
 }
 #endif

@@ -137,4 +137,28 @@ int p3m_cosmo_kick_drift(const p3m_cosmology* c, double a0, double a1, double* c
   return P3M_OK;
 }
 
+int p3m_cosmo_kdk_step(const p3m_cosmology* c, double a, double dt_factor, double* a_next,
+                       double* c_kick1, double* c_drift, double* c_kick2) {
+  if (!valid(c) || !a_next || !c_kick1 || !c_drift || !c_kick2 || !(a > 0) ||
+      !std::isfinite(a) || !(dt_factor > 0) || !std::isfinite(dt_factor))
+    return P3M_EINVAL;
+  // the step's length: dt_factor times the age at its start; the middle and
+  // the end of the step in time, then their scale factors
+  double t0 = 0, ah = 0, a1 = 0;
+  int st = p3m_cosmo_age(c, a, &t0);
+  if (st != P3M_OK) return st;
+  const double dt = dt_factor * t0;
+  if ((st = p3m_cosmo_scale_factor(c, t0 + 0.5 * dt, &ah)) != P3M_OK) return st;
+  if ((st = p3m_cosmo_scale_factor(c, t0 + dt, &a1)) != P3M_OK) return st;
+  double k1 = 0, k2 = 0, d = 0, unused = 0;
+  if ((st = p3m_cosmo_kick_drift(c, a, ah, &k1, &unused)) != P3M_OK) return st;
+  if ((st = p3m_cosmo_kick_drift(c, ah, a1, &k2, &unused)) != P3M_OK) return st;
+  if ((st = p3m_cosmo_kick_drift(c, a, a1, &unused, &d)) != P3M_OK) return st;
+  *a_next = a1;
+  *c_kick1 = k1;
+  *c_drift = d;
+  *c_kick2 = k2;
+  return P3M_OK;
+}
+
 }  // extern "C"

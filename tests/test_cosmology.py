@@ -78,3 +78,47 @@ def test_cosmology_errors(b):
                                       ctypes.byref(out)) == -4
     with pytest.raises(ValueError):
         b.Cosmology(1.0, 0.3, 0.7).age(-1.0)
+
+
+def test_kdk_step_einstein_de_sitter_closed_form(b):
+    """Omega_m = 1: a(t) = (3 H0 t / 2)^(2/3), so a step of a fraction f of
+    the age ends at a (1 + f)^(2/3) and its middle in time is at
+    a (1 + f/2)^(2/3); the kicks and the drift are the closed-form
+    integrals between them."""
+    H0, a, f = 0.7, 0.05, 0.02
+    c = b.Cosmology(H0, 1.0, 0.0)
+    a1, k1, d, k2 = c.kdk_step(a, f)
+    ah = a * (1 + 0.5 * f) ** (2.0 / 3.0)
+    assert a1 == pytest.approx(a * (1 + f) ** (2.0 / 3.0), rel=1e-12)
+    assert k1 == pytest.approx(2.0 * (math.sqrt(ah) - math.sqrt(a)) / H0, rel=1e-11)
+    assert k2 == pytest.approx(2.0 * (math.sqrt(a1) - math.sqrt(ah)) / H0, rel=1e-11)
+    assert d == pytest.approx(2.0 * (1 / math.sqrt(a) - 1 / math.sqrt(a1)) / H0, rel=1e-11)
+
+
+def test_kdk_step_matches_oracle_composition(b):
+    """Flat Lambda-CDM: the library's step against the same composition of
+    the oracle's quadrature and root finding."""
+    H0, Om, OL, a, f = 1.0, 0.3, 0.7, 0.1, 0.03
+    a1, k1, d, k2 = b.Cosmology(H0, Om, OL).kdk_step(a, f)
+    t0 = oc.age(a, H0, Om, OL)
+    ah = oc.scale_factor(t0 + 0.5 * f * t0, H0, Om, OL)
+    ae = oc.scale_factor(t0 + f * t0, H0, Om, OL)
+    assert a1 == pytest.approx(ae, rel=1e-11)
+    assert k1 == pytest.approx(oc.kick_drift(a, ah, H0, Om, OL)[0], rel=1e-10)
+    assert k2 == pytest.approx(oc.kick_drift(ah, ae, H0, Om, OL)[0], rel=1e-10)
+    assert d == pytest.approx(oc.kick_drift(a, ae, H0, Om, OL)[1], rel=1e-10)
+
+
+def test_kdk_step_errors(b):
+    import ctypes
+    cs = b.P3MCosmology(1.0, 0.3, 0.7)
+    o = [ctypes.c_double() for _ in range(4)]
+    ref = [ctypes.byref(x) for x in o]
+    L = b._lib
+    assert L.p3m_cosmo_kdk_step(None, 0.1, 0.01, *ref) == -1
+    assert L.p3m_cosmo_kdk_step(ctypes.byref(cs), 0.0, 0.01, *ref) == -1
+    assert L.p3m_cosmo_kdk_step(ctypes.byref(cs), 0.1, 0.0, *ref) == -1
+    assert L.p3m_cosmo_kdk_step(ctypes.byref(cs), 0.1, float("nan"), *ref) == -1
+    assert L.p3m_cosmo_kdk_step(ctypes.byref(cs), 0.1, 0.01, None, ref[1], ref[2], ref[3]) == -1
+    with pytest.raises(ValueError):
+        b.Cosmology(1.0, 0.3, 0.7).kdk_step(0.1, -0.5)

@@ -102,6 +102,59 @@ def test_drift_test_of_the_guide_crossing_faces():
     assert np.max(np.minimum(d, 1.0 - d)) < 1e-13
 
 
+def test_comoving_kdk_steps_against_the_oracle():
+    """Comoving leapfrog (guide Ch. 5: H0, Omega_m, Omega_Lambda, a_begin,
+    Delta t_factor; Ch. 6: comoving positions and canonical momenta): three
+    kick-drift-kick steps, each a fraction 0.05 of the age, from a = 0.02 in
+    flat Lambda-CDM. The GPU takes the library's step coefficients and its
+    FP64 P3M force; the oracle takes the same composition of its own
+    quadrature (oracle.cosmology), its own P3M force and its own kick and
+    drift. Positions agree to the force parity (1e-10 of a cell), momenta to
+    1e-9 relative."""
+    from oracle import cosmology as oc
+    from paper_1510_07621_amd import binding
+    H0, Om, OL, a0, f = 1.0, 0.3, 0.7, 0.02, 0.05
+    grid, n = 16, 3000
+    pos = ics.uniform(n, seed=77)
+    m = 1.0 / n
+    eps = 0.03 / 16
+    cos = binding.Cosmology(H0, Om, OL)
+    # GPU
+    x = dev(pos)
+    p = torch.zeros_like(x)
+    with plan(grid, n, "fp64", softening=eps) as P:
+        F = P.force(x, m)
+        a = a0
+        for _ in range(3):
+            a1, k1, d, k2 = cos.kdk_step(a, f)
+            binding.kick_drift(x, p, F, m, k1, d, 1.0)
+            P.force(x, m, out=F)
+            binding.kick(p, F, k2)
+            a = a1
+        xg, pg = host(x), host(p)
+    # oracle
+    xo, po = pos.copy(), np.zeros_like(pos)
+    Fo = o_p3m.p3m_force(xo, m, 1.0, grid, 1.25, 4.5, eps)
+    a = a0
+    for _ in range(3):
+        t0 = oc.age(a, H0, Om, OL)
+        ah = oc.scale_factor(t0 + 0.5 * f * t0, H0, Om, OL)
+        a1 = oc.scale_factor(t0 + f * t0, H0, Om, OL)
+        k1 = oc.kick_drift(a, ah, H0, Om, OL)[0]
+        k2 = oc.kick_drift(ah, a1, H0, Om, OL)[0]
+        d = oc.kick_drift(a, a1, H0, Om, OL)[1]
+        po = integrate.kick(po, Fo, k1)
+        xo = integrate.drift(xo, po, m, d, 1.0)
+        Fo = o_p3m.p3m_force(xo, m, 1.0, grid, 1.25, 4.5, eps)
+        po = integrate.kick(po, Fo, k2)
+        a = a1
+    dx = np.abs(xg - xo)
+    dx = np.minimum(dx, 1.0 - dx)
+    assert np.max(dx) <= 1e-10 / grid
+    assert np.max(np.abs(pg - po)) <= 1e-9 * np.max(np.abs(po))
+    assert np.max(np.abs(po)) > 0
+
+
 # --------------------------------------------------------------- pair counts
 
 @pytest.mark.parametrize("name,grid,n", [("uniform", 32, 32768), ("uniform", 16, 1000),
