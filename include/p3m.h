@@ -276,12 +276,14 @@ int p3m_drift_vjp(int64_t n, double* mom_bar, const double* pos_bar, const doubl
  * s < n_stages, the total duration in milliseconds of stage s over the
  * recorded calls (0 for a stage that never ran), and returns the number of
  * recorded calls (>= 0) or a negative status. Stage indices: */
-#define P3M_STAGE_BIN      0  /* cell keys, counts, scan, scatter, work list  */
+#define P3M_STAGE_BIN      0  /* cell keys, counts, scan, scatter, work list
+                                 (+ reaction offsets of the one-sided sum)     */
 #define P3M_STAGE_DEPOSIT  1  /* CIC mass deposit                              */
 #define P3M_STAGE_FFT      2  /* forward FFT, Green's function, inverse FFT   */
 #define P3M_STAGE_INTERP   3  /* finite-difference gradient + interpolation   */
 #define P3M_STAGE_PP       4  /* short-range pair loop (+ combine, unpermute) */
-#define P3M_NUM_STAGES     5
+#define P3M_STAGE_REACT    5  /* one-sided sum: gather of the reactions       */
+#define P3M_NUM_STAGES     6
 int p3m_set_timing(p3m_plan* plan, int32_t capacity);
 int p3m_stage_times(p3m_plan* plan, double* ms_out, int32_t n_stages);
 

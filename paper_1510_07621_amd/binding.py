@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("P3M_LIBRARY") or os.path.join(_HERE, "libp3m.so")
 
 P3M_OK, P3M_EINVAL, P3M_ENOMEM, P3M_EHIP, P3M_ERANGE, P3M_ESIZE = 0, -1, -2, -3, -4, -5
 P3M_FP64, P3M_FP32 = 0, 1
-STAGES = ("bin", "deposit", "fft", "interp", "pp")
+STAGES = ("bin", "deposit", "fft", "interp", "pp", "react")
 
 
 class P3MParams(ctypes.Structure):
@@ -90,6 +90,9 @@ def _load():
                                                   ctypes.POINTER(dbl)]),
         "p3m_cosmo_kick_drift": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl, dbl,
                                                 ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
+        "p3m_cosmo_kdk_step": (ctypes.c_int, [ctypes.POINTER(P3MCosmology), dbl, dbl,
+                                              ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                              ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -234,15 +237,12 @@ class Cosmology:
     def kdk_step(self, a: float, dt_factor: float):
         """One kick-drift-kick step of length dt_factor times the age at a
         (guide Ch. 5, Delta t_factor): returns (a_next, c_kick_first, c_drift,
-        c_kick_second), the kicks covering the first and second half in time."""
-        t0 = self.age(a)
-        dt = dt_factor * t0
-        a_half = self.scale_factor(t0 + 0.5 * dt)
-        a_next = self.scale_factor(t0 + dt)
-        k1, _ = self.kick_drift(a, a_half)
-        k2, _ = self.kick_drift(a_half, a_next)
-        _, d = self.kick_drift(a, a_next)
-        return a_next, k1, d, k2
+        c_kick_second), the kicks covering the first and second half in time
+        (p3m_cosmo_kdk_step)."""
+        out = [ctypes.c_double() for _ in range(4)]
+        _check(_lib.p3m_cosmo_kdk_step(ctypes.byref(self._c()), float(a), float(dt_factor),
+                                       *[ctypes.byref(o) for o in out]), "p3m_cosmo_kdk_step")
+        return tuple(o.value for o in out)
 
 
 @dataclass

@@ -117,16 +117,19 @@ template <typename T>
 hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
                      double ms, void* force, int f32, Part part) {
   hipError_t e;
+  const bool half = P->rcap > 0 && part != Part::kPM;
   {
     StageTimer t(P, P3M_STAGE_BIN);
     if ((e = launch_bin(P, n, pos, mass, ms)) != hipSuccess) return e;
     if (part != Part::kPM && (e = launch_items(P)) != hipSuccess) return e;
+    if (half && (e = launch_react_prepass(P)) != hipSuccess) return e;
   }
   if (part == Part::kP3M) {
     // The mesh part (deposit, Poisson solve) on the second stream beside the
     // pair sum, which writes its sorted acceleration; the interpolation then
     // adds the mesh acceleration and writes the force once both are done.
-    // Both read the binned particles only.
+    // Both read the binned particles only. (One-sided sum: the gather adds
+    // the reactions to the sorted acceleration first.)
     const hipStream_t main = P->stream;
     if ((e = hipEventRecord(P->ev_fork, main)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(P->stream2, P->ev_fork, 0)) != hipSuccess) return e;
@@ -145,6 +148,12 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
     {
       StageTimer t(P, P3M_STAGE_PP);
       if ((e = launch_pairs<T>(P, n, false, nullptr, f32, mass == nullptr, P->ws.acc_pm)) !=
+          hipSuccess)
+        return e;
+    }
+    if (half) {
+      StageTimer t(P, P3M_STAGE_REACT);
+      if ((e = launch_pair_gather<T>(P, n, false, mass == nullptr, P->ws.acc_pm, nullptr, 0)) !=
           hipSuccess)
         return e;
     }
@@ -168,10 +177,16 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
     }
   }
   if (part != Part::kPM) {
-    StageTimer t(P, P3M_STAGE_PP);
-    if ((e = launch_pairs<T>(P, n, part == Part::kP3M, force, f32, mass == nullptr)) !=
-        hipSuccess)
-      return e;
+    {
+      StageTimer t(P, P3M_STAGE_PP);
+      if ((e = launch_pairs<T>(P, n, false, force, f32, mass == nullptr)) != hipSuccess) return e;
+    }
+    if (half) {
+      StageTimer t(P, P3M_STAGE_REACT);
+      if ((e = launch_pair_gather<T>(P, n, false, mass == nullptr, nullptr, force, f32)) !=
+          hipSuccess)
+        return e;
+    }
   }
   return hipSuccess;
 }
@@ -201,10 +216,12 @@ hipError_t run_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass
                    const double* fbar, double* pbar, Part part) {
   hipError_t e;
   Workspace& W = P->ws;
+  const bool half = P->rcap > 0 && part != Part::kPM;
   {
     StageTimer t(P, P3M_STAGE_BIN);
     if ((e = launch_bin(P, n, pos, mass, ms)) != hipSuccess) return e;
     if (part != Part::kPM && (e = launch_items(P)) != hipSuccess) return e;
+    if (half && (e = launch_react_prepass(P)) != hipSuccess) return e;
     if ((e = launch_lambda_sort<T>(P, n, fbar)) != hipSuccess) return e;
   }
   if (part == Part::kP3M) {
@@ -237,6 +254,12 @@ hipError_t run_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass
           hipSuccess)
         return e;
     }
+    if (half) {
+      StageTimer t(P, P3M_STAGE_REACT);
+      if ((e = launch_pair_gather<T>(P, n, true, mass == nullptr, W.acc_pm, nullptr, 0)) !=
+          hipSuccess)
+        return e;
+    }
     if ((e = hipStreamWaitEvent(main, P->ev_join, 0)) != hipSuccess) return e;
     StageTimer t(P, P3M_STAGE_INTERP);
     return launch_interp_vjp<T>(P, n, pbar, W.acc_pm);
@@ -262,10 +285,16 @@ hipError_t run_vjp(p3m_plan* P, int64_t n, const double* pos, const double* mass
     }
   }
   if (part != Part::kPM) {
-    StageTimer t(P, P3M_STAGE_PP);
-    if ((e = launch_pairs_vjp<T>(P, n, part == Part::kP3M, pbar, mass == nullptr)) !=
-        hipSuccess)
-      return e;
+    {
+      StageTimer t(P, P3M_STAGE_PP);
+      if ((e = launch_pairs_vjp<T>(P, n, false, pbar, mass == nullptr)) != hipSuccess) return e;
+    }
+    if (half) {
+      StageTimer t(P, P3M_STAGE_REACT);
+      if ((e = launch_pair_gather<T>(P, n, true, mass == nullptr, nullptr, pbar, 0)) !=
+          hipSuccess)
+        return e;
+    }
   }
   return hipSuccess;
 }

@@ -158,11 +158,15 @@ hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, in
                         bool uniform_mass, void* acc_out = nullptr);
 template <typename T>
 hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
-// One-sided pair sum: per-group half-stencil offsets and partial bases
-// (before the pair kernel), and the gather of the reaction partials onto the
-// sorted action in ws.acc_pm (after it): the result goes to acc_out (sorted,
+// One-sided pair sum (plans with rcap > 0): per-group reaction offsets and
+// partial bases (after the work list, before the pair kernel, which then
+// writes the sorted action to ws.acc_pm), and the gather of the reaction
+// partials onto that action (after it): the result goes to acc_out (sorted,
 // T4) if not null, else to out in input order as m * a (float if out_fp32).
 hipError_t launch_react_prepass(p3m_plan* P);
+template <typename T>
+hipError_t launch_pair_gather(p3m_plan* P, int64_t n, bool vjp, bool uniform_mass,
+                              void* acc_out, void* out, int out_fp32);
 int64_t react_scan_tmp_size(int64_t ngroup);
 template <typename T>
 hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool uniform_mass,

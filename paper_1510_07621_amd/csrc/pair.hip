@@ -1205,28 +1205,16 @@ hipError_t launch_pair_kernel(p3m_plan* P, const PairArgs<T>& A, bool uniform_ma
   return hipGetLastError();
 }
 
-// The one-sided sum: offsets and partial bases, the pair kernel (sorted
-// action into ws.acc_pm), the gather (acc_out sorted, or out in input order).
-template <typename T, bool VJP>
-hipError_t launch_half(p3m_plan* P, int64_t n, PairArgs<T> A, bool uniform_mass,
-                       void* acc_out, void* out, int out_fp32) {
-  hipError_t e = launch_react_prepass(P);
-  if (e != hipSuccess) return e;
-  A.acc_pm = nullptr;
-  A.acc_out = (typename Vec<T>::v4*)P->ws.acc_pm;
-  A.force = nullptr;
-  if ((e = launch_pair_kernel<T, VJP>(P, A, uniform_mass, true)) != hipSuccess) return e;
-  const int tab = sizeof(T) == 4 ? P->tab_var : P->tab64_var;
-  return launch_react_gather<T>(P, n, -out_scale(A, tab, VJP), uniform_mass, acc_out, out,
-                                out_fp32);
-}
-
 template <typename T>
 hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32,
                         bool uniform_mass, void* acc_out) {
   PairArgs<T> A = make_args<T>(P, n);
-  if (P->rcap > 0 && !add_pm)
-    return launch_half<T, false>(P, n, A, uniform_mass, acc_out, force_out, force_fp32);
+  if (P->rcap > 0 && !add_pm) {
+    // one-sided sum: the sorted action into ws.acc_pm; launch_pair_gather
+    // then adds the reactions and writes the result
+    A.acc_out = (typename Vec<T>::v4*)P->ws.acc_pm;
+    return launch_pair_kernel<T, false>(P, A, uniform_mass, true);
+  }
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
   A.acc_out = (typename Vec<T>::v4*)acc_out;
   A.force = force_out;
@@ -1239,13 +1227,24 @@ hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar
                             bool uniform_mass, void* acc_out) {
   PairArgs<T> A = make_args<T>(P, n);
   A.lam = (const typename Vec<T>::v4*)P->ws.lam;
-  if (P->rcap > 0 && !add_pm)
-    return launch_half<T, true>(P, n, A, uniform_mass, acc_out, pos_bar, 0);
+  if (P->rcap > 0 && !add_pm) {
+    A.acc_out = (typename Vec<T>::v4*)P->ws.acc_pm;
+    return launch_pair_kernel<T, true>(P, A, uniform_mass, true);
+  }
   A.acc_pm = add_pm ? (const typename Vec<T>::v4*)P->ws.acc_pm : nullptr;
   A.acc_out = (typename Vec<T>::v4*)acc_out;
   A.force = pos_bar;
   A.force_fp32 = 0;
   return launch_pair_kernel<T, true>(P, A, uniform_mass, false);
+}
+
+template <typename T>
+hipError_t launch_pair_gather(p3m_plan* P, int64_t n, bool vjp, bool uniform_mass,
+                              void* acc_out, void* out, int out_fp32) {
+  const PairArgs<T> A = make_args<T>(P, n);
+  const int tab = sizeof(T) == 4 ? P->tab_var : P->tab64_var;
+  return launch_react_gather<T>(P, n, -out_scale(A, tab, vjp), uniform_mass, acc_out, out,
+                                out_fp32);
 }
 
 template <typename T>
@@ -1262,6 +1261,10 @@ template hipError_t launch_pairs<float>(p3m_plan*, int64_t, bool, void*, int, bo
 template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, bool, void*);
 template hipError_t launch_pairs_vjp<float>(p3m_plan*, int64_t, bool, double*, bool, void*);
 template hipError_t launch_pairs_vjp<double>(p3m_plan*, int64_t, bool, double*, bool, void*);
+template hipError_t launch_pair_gather<float>(p3m_plan*, int64_t, bool, bool, void*, void*,
+                                             int);
+template hipError_t launch_pair_gather<double>(p3m_plan*, int64_t, bool, bool, void*, void*,
+                                              int);
 template hipError_t launch_pair_count<float>(p3m_plan*, int64_t, int64_t*);
 template hipError_t launch_pair_count<double>(p3m_plan*, int64_t, int64_t*);
 
