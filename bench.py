@@ -42,6 +42,27 @@ HBM_PEAK_GBS = 8000.0
 HEADLINE_PARTIALS = 80      # one-sided pair sum between dense groups (clustered set)
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+PAIR_SOURCES = ("pair.hip", "react.hip")
+
+
+def counter_record(name):
+    """A committed counter summary of the pair stage (profiles/<name>.json),
+    or None when the pair kernel's or the gather's source changed after the
+    counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(PROFILES, name + ".json")) as f:
+            rec = json.load(f)
+        digest = {}
+        for src in PAIR_SOURCES:
+            with open(os.path.join(ROOT, "paper_1510_07621_amd", "csrc", src), "rb") as f:
+                digest[src] = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get("source_sha256") == digest else None
+
+
 def log(msg):
     """Progress of the legs on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -432,12 +453,25 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": None,
+            "valu": None,
             "flop_per_pair": FLOP_PER_PAIR,
             "avg_launch_ms": pair_ms,
             "avg_launch_ms_parts": {"k_pairs": st["pp"], "k_react_gather": st["react"]},
         },
         "adjoint_fwd_ratio": None,
     }
+    if args.workload == "plummer256":
+        # HBM bytes per launch of the pair stage and its VALU issue, from the
+        # committed counter runs of this workload (null once the sources changed)
+        rec = counter_record("pair_stage_plummer256_traffic")
+        if rec:
+            out["roofline"]["traffic"] = rec["bytes_per_launch"]
+        rec = counter_record("pair_stage_plummer256_valu")
+        if rec:
+            out["roofline"]["valu"] = {k: {q: v[q] for q in ("valu_issue_util", "valu_lane_util",
+                                                              "valu_issue_per_cu_clock",
+                                                              "clock_ghz")}
+                                       for k, v in rec["kernels"].items()}
     tg_head = sample_targets(w.n, args.cpu_targets, 77)
     cfg = []
     if not args.no_configs:
