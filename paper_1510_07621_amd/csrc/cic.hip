@@ -32,16 +32,34 @@ using namespace brick;
 // whose sorted ranges are staged in LDS first. NC = 1: mass, scaled by
 // 1 / h^3 (the density); NC = 3: mass times each component of a cotangent
 // (the adjoint's deposit), unscaled, to out[c * ng^3 + node].
+//
+// Heavy cells (NC = 1): a node thread that loops over the particles of its
+// eight cells takes as long as the most crowded of them, so on clustered
+// input a few threads would hold their brick for thousands of iterations.
+// A cell with more than kHeavy particles is instead reduced once, by one
+// wave (the lanes split its particles), into its eight corner sums
+// sum m (1 - t or t)_x (1 - t or t)_y (1 - t or t)_z, kept in LDS for up to
+// kHeavySlots such cells per brick; its nodes add the one sum each needs.
+// (Further heavy cells of a brick are looped over as before.)
+constexpr int kHeavy = 16;
+constexpr int kHeavySlots = 96;
+
 template <typename T, int NC>
 __global__ void __launch_bounds__(kThreads)
 k_deposit_gather(const typename Vec<T>::v4* __restrict__ rec,
                  const typename Vec<T>::v4* __restrict__ lam, const int32_t* __restrict__ start,
                  int ng, int lg, T inv_h, T scale, T* __restrict__ out) {
   constexpr int kC = kN1 * kN1 * kN1;             // cells [-1, kBrick)^3
+  constexpr bool HV = NC == 1;                    // heavy cells reduced once
   __shared__ int cs[kC], cn[kC];
+  __shared__ short hidx[HV ? kC : 1];             // slot of a heavy cell, or -1
+  __shared__ short hcell[HV ? kHeavySlots : 1];
+  __shared__ T mom[HV ? kHeavySlots : 1][8];
+  __shared__ int hcount;
   const int lb = lg - 3, mb = (1 << lb) - 1, mask = ng - 1;
   const int b = blockIdx.x;
   const int bz0 = (b & mb) * kBrick, by0 = ((b >> lb) & mb) * kBrick, bx0 = (b >> (2 * lb)) * kBrick;
+  if (HV && threadIdx.x == 0) hcount = 0;
   for (int e = threadIdx.x; e < kC; e += kThreads) {
     const int gx = (bx0 - 1 + e / (kN1 * kN1)) & mask, gy = (by0 - 1 + (e / kN1) % kN1) & mask,
               gz = (bz0 - 1 + e % kN1) & mask;
@@ -51,6 +69,48 @@ k_deposit_gather(const typename Vec<T>::v4* __restrict__ rec,
     cn[e] = start[c + 1] - lo;
   }
   __syncthreads();
+  if constexpr (HV) {
+    for (int e = threadIdx.x; e < kC; e += kThreads) {
+      short slot = -1;
+      if (cn[e] > kHeavy) {
+        const int k = atomicAdd(&hcount, 1);
+        if (k < kHeavySlots) {
+          slot = (short)k;
+          hcell[k] = (short)e;
+        }
+      }
+      hidx[e] = slot;
+    }
+    __syncthreads();
+    const int nh = min(hcount, kHeavySlots);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = wave; k < nh; k += kThreads / 64) {
+      const int e = hcell[k];
+      const int s0 = cs[e], s1 = s0 + cn[e];
+      T m8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m8[q] = T(0);
+      for (int s = s0 + lane; s < s1; s += 64) {
+        const typename Vec<T>::v4 p = rec[s];
+        const T tx = p.x * inv_h, ty = p.y * inv_h, tz = p.z * inv_h;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int a = q >> 2, bb = (q >> 1) & 1, c = q & 1;
+          m8[q] += p.w * ((a ? T(1) - tx : tx) * (bb ? T(1) - ty : ty) * (c ? T(1) - tz : tz));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m8[q] += __shfl_xor(m8[q], o, 64);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mom[k][q] = m8[q];
+      }
+    }
+    __syncthreads();
+  }
   const int64_t ncell = (int64_t)1 << (3 * lg);
   for (int node = threadIdx.x; node < kBrick * kBrick * kBrick; node += kThreads) {
     const int i = node >> 6, j = (node >> 3) & 7, k = node & 7;
@@ -64,6 +124,13 @@ k_deposit_gather(const typename Vec<T>::v4* __restrict__ rec,
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const int e = ((i + a) * kN1 + (j + bb)) * kN1 + (k + c);
+          if constexpr (HV) {
+            const int h = hidx[e];
+            if (h >= 0) {
+              acc[0] += mom[h][(a << 2) | (bb << 1) | c];
+              continue;
+            }
+          }
           const int s0 = cs[e], s1 = s0 + cn[e];
           for (int s = s0; s < s1; ++s) {
             const typename Vec<T>::v4 p = rec[s];
