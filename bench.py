@@ -480,7 +480,8 @@ def main():
         cfg.append(force_leg(binding, torch, "zeldovich128", 20,
                              legs=(("fp32", 0), ("fp64", 0))))
         cfg.append(force_leg(binding, torch, "plummer256", 5,
-                             legs=(("fp32", HEADLINE_PARTIALS), ("fp32", 0), ("fp64", 0)),
+                             legs=(("fp32", HEADLINE_PARTIALS), ("fp32", 0),
+                                   ("fp64", HEADLINE_PARTIALS), ("fp64", 0)),
                              tg=tg_head if args.workload == "plummer256" else None,
                              w=w if args.workload == "plummer256" else None,
                              pos=pos if args.workload == "plummer256" else None))
