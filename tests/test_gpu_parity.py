@@ -262,6 +262,23 @@ def test_p3m_force_parity(uniform32, precision, tol, tight):
     assert _err(F32, ref)["rms"] <= max(tol, 1e-6)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_plan_sized_for_more_particles_than_the_call(uniform32, precision, tol):
+    """The i-group edge is chosen from the plan's n_max (for a mean of 64
+    particles per group at n_max): a plan made for 16x the particles, and so
+    with smaller groups than the call's density would get, still gives the
+    oracle's force (the groups change only the work split), and so does a
+    plan for a single particle more than the call (larger groups)."""
+    w, pos, a_pp, a_pm = uniform32
+    ref = (a_pp + a_pm) * w.mass
+    for n_max in (16 * w.n, w.n + 1):
+        with plan(w.grid_n, n_max, precision, box=w.box, rs_cells=w.rs_cells,
+                  cutoff_rs=w.cutoff_rs, softening=w.softening, G=w.G) as P:
+            F = host(P.force(dev(pos), w.mass))
+        e = _err(F, ref)
+        assert e["rms"] <= tol, (n_max, e)
+
+
 def test_p3m_method_error_matches_the_oracle_against_ewald(uniform32):
     """P3M vs direct Ewald: the GPU's method error equals the oracle's to
     three significant digits (it is the same discretisation)."""
