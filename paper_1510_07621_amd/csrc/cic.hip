@@ -259,10 +259,10 @@ hipError_t launch_deposit3(p3m_plan* P, const void* lam, void* grids) {
 // per brick); the grid's edge must be a multiple of BX and BZ.
 template <typename T, int BX, int BZ>
 hipError_t launch_interp_bricks(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
-                                const void* acc_pp, T c1, T c2) {
+                                const void* acc_pp, T c1, T c2, void* sorted_out) {
   Workspace& W = P->ws;
   const int nb = (int)(P->ncell / (BX * BX * BZ));
-  typename Vec<T>::v4* acc = force_out ? nullptr : (typename Vec<T>::v4*)W.acc_pm;
+  typename Vec<T>::v4* acc = (typename Vec<T>::v4*)sorted_out;
   k_interp<T, BX, BZ><<<nb, kThreads, 0, P->stream>>>(
       (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / P->h),
       (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
@@ -272,7 +272,7 @@ hipError_t launch_interp_bricks(p3m_plan* P, int64_t n, void* force_out, int for
 
 template <typename T>
 hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
-                         const void* acc_pp) {
+                         const void* acc_pp, void* sorted_out) {
   double h = P->h;
   T c1, c2;
   if (P->prm.fd_order == 2) {
@@ -286,14 +286,17 @@ hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32
   // wave's particles are 4 runs of 16 cells. Measured at 128^3 against 8^3
   // bricks: FP32 65 -> 47 us (4 x 4 x 32: the same; 2 x 2 x 64: 55), FP64
   // 77 -> 62 us (4 x 4 x 32: 72, its LDS costing occupancy; 2 x 2 x 32: 72).
-  return launch_interp_bricks<T, 4, 16>(P, n, force_out, force_fp32, acc_pp, c1, c2);
+  // no force: the sorted mesh acceleration, to sorted_out (default: ws.acc_pm)
+  if (!force_out && !sorted_out) sorted_out = P->ws.acc_pm;
+  return launch_interp_bricks<T, 4, 16>(P, n, force_out, force_fp32, acc_pp, c1, c2,
+                                        force_out ? nullptr : sorted_out);
 }
 
 template hipError_t launch_deposit<float>(p3m_plan*);
 template hipError_t launch_deposit<double>(p3m_plan*);
 template hipError_t launch_deposit3<float>(p3m_plan*, const void*, void*);
 template hipError_t launch_deposit3<double>(p3m_plan*, const void*, void*);
-template hipError_t launch_interp<float>(p3m_plan*, int64_t, void*, int, const void*);
-template hipError_t launch_interp<double>(p3m_plan*, int64_t, void*, int, const void*);
+template hipError_t launch_interp<float>(p3m_plan*, int64_t, void*, int, const void*, void*);
+template hipError_t launch_interp<double>(p3m_plan*, int64_t, void*, int, const void*, void*);
 
 }  // namespace p3m

@@ -46,7 +46,7 @@ void free_workspace(p3m_plan* P) {
                   W.spec, W.twiddle, W.gtab,  W.counter, W.split_tab, W.split_tab64, W.lam,
                   W.grid2, W.lam_grid, W.power_acc, W.ewald_tab, W.ewald_zpair,
                   W.segrows, W.prows, W.pbrows, W.pboff, W.rowoff, W.gipre, W.gntot,
-                  W.gtot, W.gbase, W.gscan_tmp, W.rpart};
+                  W.gtot, W.gbase, W.gscan_tmp, W.rpart, W.acc_mesh};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   W = Workspace{};
@@ -128,8 +128,10 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
     // The mesh part (deposit, Poisson solve) on the second stream beside the
     // pair sum, which writes its sorted acceleration; the interpolation then
     // adds the mesh acceleration and writes the force once both are done.
-    // Both read the binned particles only. (One-sided sum: the gather adds
-    // the reactions to the sorted acceleration first.)
+    // Both read the binned particles only. One-sided sum: the interpolation
+    // also runs on the second stream (to the sorted mesh acceleration), and
+    // the gather of the reactions, after the pair sum, adds it and writes
+    // the force.
     const hipStream_t main = P->stream;
     if ((e = hipEventRecord(P->ev_fork, main)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(P->stream2, P->ev_fork, 0)) != hipSuccess) return e;
@@ -143,6 +145,11 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
         StageTimer t(P, P3M_STAGE_FFT);
         if ((e = launch_fft_poisson<T>(P)) != hipSuccess) return e;
       }
+      if (half) {
+        StageTimer t(P, P3M_STAGE_INTERP);
+        if ((e = launch_interp<T>(P, n, nullptr, f32, nullptr, P->ws.acc_mesh)) != hipSuccess)
+          return e;
+      }
       if ((e = hipEventRecord(P->ev_join, P->stream2)) != hipSuccess) return e;
     }
     {
@@ -151,13 +158,12 @@ hipError_t run_force(p3m_plan* P, int64_t n, const double* pos, const double* ma
           hipSuccess)
         return e;
     }
+    if ((e = hipStreamWaitEvent(main, P->ev_join, 0)) != hipSuccess) return e;
     if (half) {
       StageTimer t(P, P3M_STAGE_REACT);
-      if ((e = launch_pair_gather<T>(P, n, false, mass == nullptr, P->ws.acc_pm, nullptr, 0)) !=
-          hipSuccess)
-        return e;
+      return launch_pair_gather<T>(P, n, false, mass == nullptr, nullptr, force, f32,
+                                   P->ws.acc_mesh);
     }
-    if ((e = hipStreamWaitEvent(main, P->ev_join, 0)) != hipSuccess) return e;
     StageTimer t(P, P3M_STAGE_INTERP);
     return launch_interp<T>(P, n, force, f32, P->ws.acc_pm);
   }
@@ -815,6 +821,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
       if (hipMalloc(&p, (size_t)cap * 3 * real) == hipSuccess) {
         W.rpart = p;
         P->rcap = cap;
+        W.acc_mesh = dev_alloc<unsigned char>(nn * 4 * real, err);
       } else {
         (void)hipGetLastError();          // clear the failed allocation's error
       }

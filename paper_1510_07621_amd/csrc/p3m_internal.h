@@ -87,6 +87,7 @@ struct Workspace {
   long long* gbase = nullptr;   // [ngroup+1] exclusive scan of gtot; [ngroup] = total
   long long* gscan_tmp = nullptr;  // tile sums of that scan
   void* rpart = nullptr;        // [3][rcap] reaction partials (T), SoA
+  void* acc_mesh = nullptr;     // [n_max]   sorted mesh acceleration of a one-sided force (T4)
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)
   void* grid2 = nullptr;        // [ng^3]    second real grid (divergence, then psi)
@@ -152,7 +153,7 @@ template <typename T>
 hipError_t launch_fft_poisson(p3m_plan* P);
 template <typename T>
 hipError_t launch_interp(p3m_plan* P, int64_t n, void* force_out, int force_fp32,
-                         const void* acc_pp = nullptr);
+                         const void* acc_pp = nullptr, void* sorted_out = nullptr);
 template <typename T>
 hipError_t launch_pairs(p3m_plan* P, int64_t n, bool add_pm, void* force_out, int force_fp32,
                         bool uniform_mass, void* acc_out = nullptr);
@@ -166,11 +167,13 @@ hipError_t launch_pair_count(p3m_plan* P, int64_t n, int64_t* count_out);
 hipError_t launch_react_prepass(p3m_plan* P);
 template <typename T>
 hipError_t launch_pair_gather(p3m_plan* P, int64_t n, bool vjp, bool uniform_mass,
-                              void* acc_out, void* out, int out_fp32);
+                              void* acc_out, void* out, int out_fp32,
+                              const void* acc_add = nullptr);
 int64_t react_scan_tmp_size(int64_t ngroup);
 template <typename T>
 hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool uniform_mass,
-                               void* acc_out, void* out, int out_fp32);
+                               void* acc_out, void* out, int out_fp32,
+                               const void* acc_add = nullptr);
 template <typename T>
 hipError_t launch_tables(p3m_plan* P);
 

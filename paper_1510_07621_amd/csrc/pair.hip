@@ -1240,11 +1240,11 @@ hipError_t launch_pairs_vjp(p3m_plan* P, int64_t n, bool add_pm, double* pos_bar
 
 template <typename T>
 hipError_t launch_pair_gather(p3m_plan* P, int64_t n, bool vjp, bool uniform_mass,
-                              void* acc_out, void* out, int out_fp32) {
+                              void* acc_out, void* out, int out_fp32, const void* acc_add) {
   const PairArgs<T> A = make_args<T>(P, n);
   const int tab = sizeof(T) == 4 ? P->tab_var : P->tab64_var;
   return launch_react_gather<T>(P, n, -out_scale(A, tab, vjp), uniform_mass, acc_out, out,
-                                out_fp32);
+                                out_fp32, acc_add);
 }
 
 template <typename T>
@@ -1262,9 +1262,9 @@ template hipError_t launch_pairs<double>(p3m_plan*, int64_t, bool, void*, int, b
 template hipError_t launch_pairs_vjp<float>(p3m_plan*, int64_t, bool, double*, bool, void*);
 template hipError_t launch_pairs_vjp<double>(p3m_plan*, int64_t, bool, double*, bool, void*);
 template hipError_t launch_pair_gather<float>(p3m_plan*, int64_t, bool, bool, void*, void*,
-                                             int);
+                                               int, const void*);
 template hipError_t launch_pair_gather<double>(p3m_plan*, int64_t, bool, bool, void*, void*,
-                                              int);
+                                                int, const void*);
 template hipError_t launch_pair_count<float>(p3m_plan*, int64_t, int64_t*);
 template hipError_t launch_pair_count<double>(p3m_plan*, int64_t, int64_t*);
 

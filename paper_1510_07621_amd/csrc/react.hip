@@ -234,6 +234,7 @@ struct GatherArgs {
   int64_t n;
   double rscale;                                 // -(the pair kernel's output scale)
   const typename Vec<T>::v4* __restrict__ acc;   // sorted action (acceleration)
+  const typename Vec<T>::v4* __restrict__ add;   // sorted acceleration added at the end, or null
   typename Vec<T>::v4* __restrict__ acc_out;     // sorted result, or null
   const int32_t* __restrict__ perm;
   void* __restrict__ out;                        // input-order result m * a, or null
@@ -261,7 +262,8 @@ k_react_gather(GatherArgs<T> A) {
   const int ng = 1 << A.lg, mask = ng - 1, G = A.G, lgG = A.lgG;
   const int lgd = A.lg - lgG;
   const T4 rs = A.rec[s];
-  T4 a = A.acc[s];
+  const T4 a = A.acc[s];
+  double ax = (double)a.x, ay = (double)a.y, az = (double)a.z;   // the result
   const long long total = A.gbase[A.ngroup];
   const int c = A.skey[s];
   const int cz = c & mask, cy = (c >> A.lg) & mask, cx = c >> (2 * A.lg);
@@ -328,26 +330,34 @@ k_react_gather(GatherArgs<T> A) {
       }
     }
     const double f = UM ? A.rscale * (double)rs.w : A.rscale;
-    a.x = (T)((double)a.x + f * (double)sx);
-    a.y = (T)((double)a.y + f * (double)sy);
-    a.z = (T)((double)a.z + f * (double)sz);
+    ax += f * (double)sx;
+    ay += f * (double)sy;
+    az += f * (double)sz;
+  }
+  if (A.add) {                         // the mesh part (P3M force)
+    const T4 b = A.add[s];
+    ax += (double)b.x;
+    ay += (double)b.y;
+    az += (double)b.z;
   }
   if (A.acc_out) {
-    A.acc_out[s] = a;
+    T4 o;
+    o.x = (T)ax; o.y = (T)ay; o.z = (T)az; o.w = T(0);
+    A.acc_out[s] = o;
     return;
   }
   const int64_t i = A.perm[s];
   const double m = (double)rs.w;
   if (A.out_fp32) {
     float* F = (float*)A.out;
-    F[i] = (float)(m * (double)a.x);
-    F[A.n + i] = (float)(m * (double)a.y);
-    F[2 * A.n + i] = (float)(m * (double)a.z);
+    F[i] = (float)(m * ax);
+    F[A.n + i] = (float)(m * ay);
+    F[2 * A.n + i] = (float)(m * az);
   } else {
     double* F = (double*)A.out;
-    F[i] = m * (double)a.x;
-    F[A.n + i] = m * (double)a.y;
-    F[2 * A.n + i] = m * (double)a.z;
+    F[i] = m * ax;
+    F[A.n + i] = m * ay;
+    F[2 * A.n + i] = m * az;
   }
 }
 
@@ -378,7 +388,7 @@ int64_t react_scan_tmp_size(int64_t ngroup) { return (ngroup + kScan64Tile - 1) 
 
 template <typename T>
 hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool uniform_mass,
-                               void* acc_out, void* out, int out_fp32) {
+                               void* acc_out, void* out, int out_fp32, const void* acc_add) {
   Workspace& W = P->ws;
   GatherArgs<T> A{};
   A.rec = (const typename Vec<T>::v4*)W.rec;
@@ -400,6 +410,7 @@ hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool unifo
   A.n = n;
   A.rscale = rscale;
   A.acc = (const typename Vec<T>::v4*)W.acc_pm;
+  A.add = (const typename Vec<T>::v4*)acc_add;
   A.acc_out = (typename Vec<T>::v4*)acc_out;
   A.perm = W.perm;
   A.out = out;
@@ -412,8 +423,8 @@ hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool unifo
 }
 
 template hipError_t launch_react_gather<float>(p3m_plan*, int64_t, double, bool, void*, void*,
-                                               int);
+                                               int, const void*);
 template hipError_t launch_react_gather<double>(p3m_plan*, int64_t, double, bool, void*, void*,
-                                                int);
+                                                int, const void*);
 
 }  // namespace p3m
