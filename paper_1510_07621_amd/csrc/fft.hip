@@ -1,7 +1,8 @@
 // Hand-written 3-D real-to-complex FFT Poisson solve on the PM grid.
 //
 // Layout: the real grid is [x][y][z] (z fastest, ng^3 values); the spectrum
-// is [kx][ky][kz] with kz = 0..ng/2 (ng * ng * (ng/2 + 1) complex values).
+// is [kx][ky][kz] with kz = 0..ng/2, each (kx, ky) row of ng/2 + 1 values
+// padded to spec_stride(ng) so that rows start on cache-line boundaries.
 // Five passes, each reading and writing the grid once, every transform done
 // in LDS:
 //   1. z, real -> complex: each z-line of ng reals is transformed as ng/2
@@ -34,7 +35,17 @@ constexpr int kLdsElems = 2048;   // complex values staged per block
 // neighbouring threads fall in different banks.
 constexpr int kPadShift = 4;      // (3 and 5 measured the same; none 2-4 % slower at 256^3)
 __device__ __forceinline__ int pd(int i) { return i + (i >> kPadShift); }
-inline size_t padded(size_t elems) { return elems + (elems >> kPadShift) + 1; }
+__host__ __device__ inline int padded(int elems) { return elems + (elems >> kPadShift) + 1; }
+
+// The twiddle table (ng/2 values) is staged in LDS after a block's values,
+// so the butterflies read it there rather than through the vector cache.
+template <typename T2>
+__device__ __forceinline__ T2* stage_twiddles(T2* buf, int staged, const T2* __restrict__ tw,
+                                              int ng) {
+  T2* t = buf + padded(staged);
+  for (int i = threadIdx.x; i < (ng >> 1); i += blockDim.x) t[i] = tw[i];
+  return t;
+}
 
 template <typename T2>
 __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
@@ -154,13 +165,15 @@ k_fft_z_r2c(const T* __restrict__ grid, typename Vec<T>::v2* __restrict__ spec, 
   T2* buf = reinterpret_cast<T2*>(smem_raw);
   const int M = ng >> 1, lgM = lg - 1;
   const int64_t line0 = (int64_t)blockIdx.x * nl;
+  const int Ms = spec_stride(ng);
   const T2* in = reinterpret_cast<const T2*>(grid);
   for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
     int b = idx >> lgM, m = idx & (M - 1);
     buf[pd(b * M + brev(m, lgM))] = in[(line0 + b) * M + m];
   }
+  const T2* twl = stage_twiddles(buf, nl * M, tw, ng);
   __syncthreads();
-  fft_dit<T, false>(buf, nl, M, lgM, tw, ng);
+  fft_dit<T, false>(buf, nl, M, lgM, twl, ng);
   const int M1 = M + 1;
   for (int idx = threadIdx.x; idx < nl * M1; idx += kThreads) {
     int b = idx / M1, k = idx - b * M1;
@@ -172,11 +185,11 @@ k_fft_z_r2c(const T* __restrict__ grid, typename Vec<T>::v2* __restrict__ spec, 
     E.x = T(0.5) * (zk.x + zc.x); E.y = T(0.5) * (zk.y + zc.y);
     O.x = T(0.5) * (zk.y - zc.y); O.y = -T(0.5) * (zk.x - zc.x);
     T2 w;
-    if (k < M) w = tw[k]; else { w.x = T(-1); w.y = T(0); }
+    if (k < M) w = twl[k]; else { w.x = T(-1); w.y = T(0); }
     T2 wo = cmul(w, O);
     T2 X;
     X.x = E.x + wo.x; X.y = E.y + wo.y;
-    spec[(line0 + b) * M1 + k] = X;
+    spec[(line0 + b) * Ms + k] = X;
   }
 }
 
@@ -188,11 +201,11 @@ k_fft_z_c2r(const typename Vec<T>::v2* __restrict__ spec, T* __restrict__ grid, 
   using T2 = typename Vec<T>::v2;
   extern __shared__ unsigned char smem_raw[];
   T2* buf = reinterpret_cast<T2*>(smem_raw);
-  const int M = ng >> 1, lgM = lg - 1, M1 = M + 1;
+  const int M = ng >> 1, lgM = lg - 1, Ms = spec_stride(ng);
   const int64_t line0 = (int64_t)blockIdx.x * nl;
   for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
     int b = idx >> lgM, k = idx & (M - 1);
-    const T2* row = spec + (line0 + b) * M1;
+    const T2* row = spec + (line0 + b) * Ms;
     T2 xk = row[k], xc = row[M - k];
     xc.y = -xc.y;
     // E = X_k + conj X_{M-k},  O = (X_k - conj X_{M-k}) * conj(W^k),  Z = E + i O
@@ -205,8 +218,9 @@ k_fft_z_c2r(const typename Vec<T>::v2* __restrict__ spec, T* __restrict__ grid, 
     Z.x = E.x - O.y; Z.y = E.y + O.x;
     buf[pd(b * M + k)] = Z;
   }
+  const T2* twl = stage_twiddles(buf, nl * M, tw, ng);
   __syncthreads();
-  fft_dif<T, true>(buf, nl, M, lgM, tw, ng);
+  fft_dif<T, true>(buf, nl, M, lgM, twl, ng);
   T2* out = reinterpret_cast<T2*>(grid);
   for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
     int b = idx >> lgM, m = idx & (M - 1);
@@ -223,23 +237,24 @@ k_fft_y(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   using T2 = typename Vec<T>::v2;
   extern __shared__ unsigned char smem_raw[];
   T2* buf = reinterpret_cast<T2*>(smem_raw);
-  const int M1 = (ng >> 1) + 1;
+  const int M1 = (ng >> 1) + 1, Ms = spec_stride(ng);
   const int nchunk = (M1 + kc - 1) / kc;
   const int x = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
-  T2* plane = spec + (int64_t)x * ng * M1 + kz0;
+  T2* plane = spec + (int64_t)x * ng * Ms + kz0;
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
     int y = idx / kc, c = idx - y * kc;
     T2 v;
-    if (c < kn) v = plane[(int64_t)y * M1 + c]; else { v.x = T(0); v.y = T(0); }
+    if (c < kn) v = plane[(int64_t)y * Ms + c]; else { v.x = T(0); v.y = T(0); }
     buf[pd(c * ng + (INV ? y : brev(y, lg)))] = v;
   }
+  const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
   __syncthreads();
-  if (INV) fft_dif<T, true>(buf, kc, ng, lg, tw, ng);
-  else fft_dit<T, false>(buf, kc, ng, lg, tw, ng);
+  if (INV) fft_dif<T, true>(buf, kc, ng, lg, twl, ng);
+  else fft_dit<T, false>(buf, kc, ng, lg, twl, ng);
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
     int y = idx / kc, c = idx - y * kc;
-    if (c < kn) plane[(int64_t)y * M1 + c] = buf[pd(c * ng + (INV ? brev(y, lg) : y))];
+    if (c < kn) plane[(int64_t)y * Ms + c] = buf[pd(c * ng + (INV ? brev(y, lg) : y))];
   }
 }
 
@@ -253,20 +268,21 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   using T2 = typename Vec<T>::v2;
   extern __shared__ unsigned char smem_raw[];
   T2* buf = reinterpret_cast<T2*>(smem_raw);
-  const int M1 = (ng >> 1) + 1;
+  const int M1 = (ng >> 1) + 1, Ms = spec_stride(ng);
   const int nchunk = (M1 + kc - 1) / kc;
   const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
-  const int64_t xs = (int64_t)ng * M1;
-  T2* col = spec + (int64_t)y * M1 + kz0;
+  const int64_t xs = (int64_t)ng * Ms;
+  T2* col = spec + (int64_t)y * Ms + kz0;
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
     int x = idx / kc, c = idx - x * kc;
     T2 v;
     if (c < kn) v = col[x * xs + c]; else { v.x = T(0); v.y = T(0); }
     buf[pd(c * ng + brev(x, lg))] = v;
   }
+  const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
   __syncthreads();
-  fft_dit<T, false>(buf, kc, ng, lg, tw, ng);
+  fft_dit<T, false>(buf, kc, ng, lg, twl, ng);
   const T ey = etab[y], k2y = k2tab[y];
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
     int c = idx >> lg, kx = idx & (ng - 1);
@@ -281,7 +297,7 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
     buf[pd(idx)] = v;
   }
   __syncthreads();
-  fft_dif<T, true>(buf, kc, ng, lg, tw, ng);
+  fft_dif<T, true>(buf, kc, ng, lg, twl, ng);
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
     int x = idx / kc, c = idx - x * kc;
     if (c < kn) col[x * xs + c] = buf[pd(c * ng + brev(x, lg))];
@@ -303,12 +319,12 @@ k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int 
   extern __shared__ unsigned char smem_raw[];
   T2* buf = reinterpret_cast<T2*>(smem_raw);
   __shared__ double hist[3 * kMaxPowerBins + 1];
-  const int M1 = (ng >> 1) + 1;
+  const int M1 = (ng >> 1) + 1, Ms = spec_stride(ng);
   const int nchunk = (M1 + kc - 1) / kc;
   const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
-  const int64_t xs = (int64_t)ng * M1;
-  const T2* col = spec + (int64_t)y * M1 + kz0;
+  const int64_t xs = (int64_t)ng * Ms;
+  const T2* col = spec + (int64_t)y * Ms + kz0;
   for (int i = threadIdx.x; i < 3 * nbins + 1; i += kThreads) hist[i] = 0.0;
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
     int x = idx / kc, c = idx - x * kc;
@@ -316,8 +332,9 @@ k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int 
     if (c < kn) v = col[x * xs + c]; else { v.x = T(0); v.y = T(0); }
     buf[pd(c * ng + brev(x, lg))] = v;
   }
+  const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
   __syncthreads();
-  fft_dit<T, false>(buf, kc, ng, lg, tw, ng);     // ends with a barrier
+  fft_dit<T, false>(buf, kc, ng, lg, twl, ng);     // ends with a barrier
   const int half = ng >> 1;
   const int ny = y < half ? y : y - ng;
   for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
@@ -439,13 +456,13 @@ hipError_t launch_fft_poisson(p3m_plan* P) {
   // z passes: nl lines per block
   int nl = pow2_floor(kLdsElems / M);
   if (nl > ng * ng) nl = ng * ng;
-  size_t lds_z = padded((size_t)nl * M) * sizeof(T2);
+  size_t lds_z = (size_t)(padded(nl * M) + M) * sizeof(T2);
   unsigned blocks_z = (unsigned)((int64_t)ng * ng / nl);
   // y / x passes: kc kz-columns per block
   int kc = kLdsElems / ng;
   if (kc > 8) kc = 8;      // 8 columns per block: twice the blocks of 16 (measured 6 % faster at 128^3)
   if (kc < 1) kc = 1;
-  size_t lds_c = padded((size_t)kc * ng) * sizeof(T2);
+  size_t lds_c = (size_t)(padded(kc * ng) + M) * sizeof(T2);
   unsigned nchunk = (unsigned)((M1 + kc - 1) / kc);
   const T* etab = (const T*)W.gtab;
   T gconst = (T)(-4.0 * M_PI * P->prm.G / ((double)ng * ng * ng));
@@ -472,12 +489,12 @@ hipError_t launch_power_spectrum(p3m_plan* P, int nbins, double r_tophat, double
   if (e != hipSuccess) return e;
   int nl = pow2_floor(kLdsElems / M);
   if (nl > ng * ng) nl = ng * ng;
-  size_t lds_z = padded((size_t)nl * M) * sizeof(T2);
+  size_t lds_z = (size_t)(padded(nl * M) + M) * sizeof(T2);
   unsigned blocks_z = (unsigned)((int64_t)ng * ng / nl);
   int kc = kLdsElems / ng;
   if (kc > 8) kc = 8;      // 8 columns per block: twice the blocks of 16 (measured 6 % faster at 128^3)
   if (kc < 1) kc = 1;
-  size_t lds_c = padded((size_t)kc * ng) * sizeof(T2);
+  size_t lds_c = (size_t)(padded(kc * ng) + M) * sizeof(T2);
   unsigned nchunk = (unsigned)((M1 + kc - 1) / kc);
   k_fft_z_r2c<T><<<blocks_z, kThreads, lds_z, s>>>((const T*)W.grid, spec, ng, lg, nl, tw);
   k_fft_y<T, false><<<ng * nchunk, kThreads, lds_c, s>>>(spec, ng, lg, kc, tw);

@@ -765,7 +765,7 @@ int p3m_plan_create(const p3m_params* prm, int64_t n_max, void* hip_stream, p3m_
     return st;
   }
   P->stream = (hipStream_t)hip_stream;
-  const int64_t nspec = (int64_t)q.grid_n * q.grid_n * (q.grid_n / 2 + 1);
+  const int64_t nspec = (int64_t)q.grid_n * q.grid_n * p3m::spec_stride(q.grid_n);
   const size_t real = q.precision == P3M_FP32 ? sizeof(float) : sizeof(double);
   const int64_t nn = n_max > 0 ? n_max : 1;
 

@@ -29,6 +29,12 @@ constexpr int kSplitBins = 64;    // pieces of the split-factor tables
 constexpr int kSplitCoef64 = 7;   // coefficients per piece of the FP64 table (degree 6)
 constexpr double kGroupTarget = 64.0;  // mean particles per i-group the plan aims for
 constexpr int kMaxPowerBins = 512;     // shells of the power spectrum
+// Row stride of the half-complex spectrum along kz: the ng/2 + 1 values of a
+// row padded to a multiple of 16, so that every row, and every 8- or
+// 16-column chunk of one, starts on a 64- (FP32) or 128-byte (FP64) boundary.
+// (With the odd ng/2 + 1 as stride each chunk of a row read by the y and x
+// passes straddled two cache lines.)
+__host__ __device__ inline int spec_stride(int ng) { return ((ng >> 1) + 1 + 15) & ~15; }
 // Reaction partials a plan holds for the one-sided pair sum by default, per
 // particle and in all (at the workloads' settings 34 per particle on a
 // displaced lattice, 64 on the 256^3 Plummer mix).
@@ -63,7 +69,7 @@ struct Workspace {
   void* rec = nullptr;          // [n_max]   sorted particle records (T4)
   void* acc_pm = nullptr;       // [n_max]   PM acceleration in sorted order (T4)
   void* grid = nullptr;         // [ng^3]    real grid (density, then potential)
-  void* spec = nullptr;         // [ng*ng*(ng/2+1)] half-complex spectrum (T2)
+  void* spec = nullptr;         // [ng*ng*spec_stride(ng)] half-complex spectrum (T2), kz fastest
   void* twiddle = nullptr;      // [ng/2]    exp(-2 pi i k / ng) (T2)
   void* gtab = nullptr;         // [2*ng]    Green's function factor tables (T)
   unsigned long long* counter = nullptr;  // [1] pair-count scratch
