@@ -83,6 +83,9 @@ def parse():
                     help="skip the adjoint/forward timing of the differentiable leapfrog")
     ap.add_argument("--cpu-targets", type=int, default=16384,
                     help="particles whose short-range force the CPU oracle evaluates")
+    ap.add_argument("--mesh-only", action="store_true",
+                    help="time only the mesh stages (pm_force with nothing beside it) and "
+                         "print them as one JSON line (the mesh stages' profiling command)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a plain copy "
                          "of known size, to scale memory counters in a profiled run)")
@@ -407,6 +410,12 @@ def main():
     import torch
     from paper_1510_07621_amd import binding, ics
 
+    if args.mesh_only:
+        out = {"mesh": [mesh_leg(binding, torch, name, prec)
+                        for name in ("zeldovich128", "plummer256") for prec in ("fp32", "fp64")]}
+        copy_calibration(torch, args, out)
+        print(json.dumps(out))
+        return
     w = ics.workload(args.workload)
     pos = w.positions()
     partials = HEADLINE_PARTIALS if args.workload == "plummer256" else 0
@@ -540,6 +549,13 @@ def main():
             config_errors(leg, sample, ref if leg["workload"] == args.workload else None)
         out["ewald"] = ewald_cpu_leg(torch, binding)
         log("Ewald leg done")
+    copy_calibration(torch, args, out)
+    print(json.dumps(out))
+
+
+def copy_calibration(torch, args, out):
+    """A plain device-to-device copy of known size after the run, whose memory
+    counters scale those of the kernels in a profiled run."""
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
@@ -548,7 +564,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
-    print(json.dumps(out))
 
 
 if __name__ == "__main__":

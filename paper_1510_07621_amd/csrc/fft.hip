@@ -59,23 +59,75 @@ __device__ __forceinline__ int brev(int v, int bits) {
   return bits ? (int)(__brev((unsigned)v) >> (32 - bits)) : 0;
 }
 
-// nb independent length-len transforms in buf (contiguous, buf[b*len + i]).
-// Twiddles: tw[k] = exp(-2 pi i k / twn), k < twn/2; inverse uses conjugates.
-// The radix-2 levels run kGroup at a time: a thread loads the 2^g elements
-// that g consecutive levels combine among themselves (positions
-// base + j + m 2^l0, m < 2^g), does the g levels' butterflies in registers
-// and stores them back, so a transform of length 2^L takes ceil(L / kGroup)
-// barriers instead of L. Every element sees the same butterflies with the
-// same twiddles, in the same level order, as one level at a time.
+// The radix-2 levels run kGroup at a time: a task holds in registers the 2^g
+// elements that g consecutive levels l0 .. l0 + g - 1 combine among
+// themselves (positions p0 + m 2^l0, m < 2^g, p0 = base + j with j < 2^l0),
+// does the g levels' butterflies and stores them back, so a transform of
+// length 2^L takes ceil(L / kGroup) exchanges instead of L. Every element
+// sees the same butterflies with the same twiddles, in the same level
+// order, as one level at a time. Twiddles: tw[k] = exp(-2 pi i k / twn),
+// k < twn/2; the inverse uses their conjugates.
 constexpr int kGroup = 3;    // measured: 2 and 4 levels per group were slower (256^3: 0.35, 0.55 ms)
 
-// Decimation in time (bit-reversed input, natural output), levels ascending.
+// Decimation in time (bit-reversed input, natural output): levels ascending.
 template <typename T, bool INV>
-__device__ void fft_dit(typename Vec<T>::v2* buf, int nb, int len, int lglen,
-                        const typename Vec<T>::v2* __restrict__ tw, int twn) {
+__device__ __forceinline__ void dit_levels(typename Vec<T>::v2 (&x)[1 << kGroup], int g, int j,
+                                           int l0, const typename Vec<T>::v2* tw, int twn) {
   using T2 = typename Vec<T>::v2;
-  for (int l0 = 0; l0 < lglen; l0 += kGroup) {
-    const int g = min(kGroup, lglen - l0);
+#pragma unroll
+  for (int t = 0; t < kGroup; ++t) {
+    if (t >= g) break;
+    const int tstride = twn >> (l0 + t + 1);
+#pragma unroll
+    for (int m = 0; m < (1 << kGroup); ++m) {
+      if (m >= (1 << g) || (m & (1 << t))) continue;
+      const int m1 = m | (1 << t);
+      const int r = j + ((m & ((1 << t) - 1)) << l0);
+      T2 w = tw[r * tstride];
+      if (INV) w.y = -w.y;
+      const T2 a = x[m], c = cmul(x[m1], w);
+      x[m].x = a.x + c.x; x[m].y = a.y + c.y;
+      x[m1].x = a.x - c.x; x[m1].y = a.y - c.y;
+    }
+  }
+}
+
+// Decimation in frequency (natural input, bit-reversed output): levels
+// descending.
+template <typename T, bool INV>
+__device__ __forceinline__ void dif_levels(typename Vec<T>::v2 (&x)[1 << kGroup], int g, int j,
+                                           int l0, const typename Vec<T>::v2* tw, int twn) {
+  using T2 = typename Vec<T>::v2;
+#pragma unroll
+  for (int t = kGroup - 1; t >= 0; --t) {
+    if (t >= g) continue;
+    const int tstride = twn >> (l0 + t + 1);
+#pragma unroll
+    for (int m = 0; m < (1 << kGroup); ++m) {
+      if (m >= (1 << g) || (m & (1 << t))) continue;
+      const int m1 = m | (1 << t);
+      const int r = j + ((m & ((1 << t) - 1)) << l0);
+      T2 w = tw[r * tstride];
+      if (INV) w.y = -w.y;
+      const T2 a = x[m], c = x[m1];
+      T2 d;
+      x[m].x = a.x + c.x; x[m].y = a.y + c.y;
+      d.x = a.x - c.x; d.y = a.y - c.y;
+      x[m1] = cmul(d, w);
+    }
+  }
+}
+
+// nb independent length-len transforms in buf (contiguous, buf[b*len + i]),
+// all levels through LDS (the z passes).
+template <typename T, bool DIT, bool INV>
+__device__ void fft_lines(typename Vec<T>::v2* buf, int nb, int len, int lglen,
+                          const typename Vec<T>::v2* __restrict__ tw, int twn) {
+  using T2 = typename Vec<T>::v2;
+  for (int k = 0; k < lglen; k += kGroup) {
+    // DIT: levels from the bottom up; DIF: from the top down
+    const int g = min(kGroup, lglen - k);
+    const int l0 = DIT ? k : lglen - k - g;
     const int tasks = len >> g;                 // per transform
     const int lgt = lglen - g;
     for (int q = threadIdx.x; q < nb * tasks; q += blockDim.x) {
@@ -86,72 +138,13 @@ __device__ void fft_dit(typename Vec<T>::v2* buf, int nb, int len, int lglen,
 #pragma unroll
       for (int m = 0; m < (1 << kGroup); ++m)
         if (m < (1 << g)) x[m] = buf[pd(p0 + (m << l0))];
-#pragma unroll
-      for (int t = 0; t < kGroup; ++t) {
-        if (t >= g) break;
-        const int tstride = twn >> (l0 + t + 1);
-#pragma unroll
-        for (int m = 0; m < (1 << kGroup); ++m) {
-          if (m >= (1 << g) || (m & (1 << t))) continue;
-          const int m1 = m | (1 << t);
-          const int r = j + ((m & ((1 << t) - 1)) << l0);
-          T2 w = tw[r * tstride];
-          if (INV) w.y = -w.y;
-          const T2 a = x[m], c = cmul(x[m1], w);
-          x[m].x = a.x + c.x; x[m].y = a.y + c.y;
-          x[m1].x = a.x - c.x; x[m1].y = a.y - c.y;
-        }
-      }
+      if (DIT) dit_levels<T, INV>(x, g, j, l0, tw, twn);
+      else dif_levels<T, INV>(x, g, j, l0, tw, twn);
 #pragma unroll
       for (int m = 0; m < (1 << kGroup); ++m)
         if (m < (1 << g)) buf[pd(p0 + (m << l0))] = x[m];
     }
     __syncthreads();
-  }
-}
-
-// Decimation in frequency (natural input, bit-reversed output), levels
-// descending.
-template <typename T, bool INV>
-__device__ void fft_dif(typename Vec<T>::v2* buf, int nb, int len, int lglen,
-                        const typename Vec<T>::v2* __restrict__ tw, int twn) {
-  using T2 = typename Vec<T>::v2;
-  for (int lhi = lglen; lhi > 0;) {
-    const int g = min(kGroup, lhi), l0 = lhi - g;
-    const int tasks = len >> g;
-    const int lgt = lglen - g;
-    for (int q = threadIdx.x; q < nb * tasks; q += blockDim.x) {
-      const int bi = q >> lgt, rem = q & (tasks - 1);
-      const int j = rem & ((1 << l0) - 1), base = (rem >> l0) << (l0 + g);
-      const int p0 = bi * len + base + j;
-      T2 x[1 << kGroup];
-#pragma unroll
-      for (int m = 0; m < (1 << kGroup); ++m)
-        if (m < (1 << g)) x[m] = buf[pd(p0 + (m << l0))];
-#pragma unroll
-      for (int t = kGroup - 1; t >= 0; --t) {
-        if (t >= g) continue;
-        const int tstride = twn >> (l0 + t + 1);
-#pragma unroll
-        for (int m = 0; m < (1 << kGroup); ++m) {
-          if (m >= (1 << g) || (m & (1 << t))) continue;
-          const int m1 = m | (1 << t);
-          const int r = j + ((m & ((1 << t) - 1)) << l0);
-          T2 w = tw[r * tstride];
-          if (INV) w.y = -w.y;
-          const T2 a = x[m], c = x[m1];
-          T2 d;
-          x[m].x = a.x + c.x; x[m].y = a.y + c.y;
-          d.x = a.x - c.x; d.y = a.y - c.y;
-          x[m1] = cmul(d, w);
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < (1 << kGroup); ++m)
-        if (m < (1 << g)) buf[pd(p0 + (m << l0))] = x[m];
-    }
-    __syncthreads();
-    lhi = l0;
   }
 }
 
@@ -173,7 +166,7 @@ k_fft_z_r2c(const T* __restrict__ grid, typename Vec<T>::v2* __restrict__ spec, 
   }
   const T2* twl = stage_twiddles(buf, nl * M, tw, ng);
   __syncthreads();
-  fft_dit<T, false>(buf, nl, M, lgM, twl, ng);
+  fft_lines<T, true, false>(buf, nl, M, lgM, twl, ng);
   const int M1 = M + 1;
   for (int idx = threadIdx.x; idx < nl * M1; idx += kThreads) {
     int b = idx / M1, k = idx - b * M1;
@@ -220,11 +213,144 @@ k_fft_z_c2r(const typename Vec<T>::v2* __restrict__ spec, T* __restrict__ grid, 
   }
   const T2* twl = stage_twiddles(buf, nl * M, tw, ng);
   __syncthreads();
-  fft_dif<T, true>(buf, nl, M, lgM, twl, ng);
+  fft_lines<T, false, true>(buf, nl, M, lgM, twl, ng);
   T2* out = reinterpret_cast<T2*>(grid);
   for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
     int b = idx >> lgM, m = idx & (M - 1);
     out[(line0 + b) * M + m] = buf[pd(b * M + brev(m, lgM))];
+  }
+}
+
+
+// ---- Column passes (y and x): kc columns of one plane per block ----
+// A block transforms kc columns (adjacent kz values) of length ng = 2^lg
+// along y or x. In LDS element i of column c sits at pd(i kc + c), so the kc
+// columns of one row are adjacent. The levels go in groups: the lowest
+// lg mod 3 (3 if none) first, then three at a time. A task is one column
+// and the 2^g elements of one level group; consecutive threads take
+// consecutive columns, so the kc columns of a row move as one contiguous
+// run of global memory. The first group of a transform loads its elements
+// from global memory and the last stores them there: only the groups
+// between pass through LDS (at 256 points, one exchange per transform; the
+// x pass's forward top group, the Green's function and the inverse top
+// group share one task).
+__device__ __forceinline__ int low_group(int lg) {
+  const int r = lg % kGroup;
+  return r ? r : kGroup;
+}
+
+struct ColGroup {
+  int l0, g;
+};
+// Level group k (ascending from the bottom) of a length-2^lg transform.
+__device__ __forceinline__ ColGroup col_group_levels(int lg, int k) {
+  const int low = low_group(lg);
+  return k == 0 ? ColGroup{0, low} : ColGroup{low + kGroup * (k - 1), kGroup};
+}
+__device__ __forceinline__ int col_groups(int lg) { return 1 + (lg - low_group(lg)) / kGroup; }
+
+// One level group over the block's columns: LD(p, c) gives element p of
+// column c, MID(x, p0, l0, g, c, j) acts on the task's values after the
+// butterflies, ST(p, c, v) takes them back.
+template <typename T, bool DIT, bool INV, typename LD, typename MID, typename ST>
+__device__ __forceinline__ void col_group(int kc, int lgkc, int lg, ColGroup lv,
+                                          const typename Vec<T>::v2* tw, int twn, LD ld, MID mid,
+                                          ST st) {
+  using T2 = typename Vec<T>::v2;
+  const int l0 = lv.l0, g = lv.g;
+  const int tasks = kc << (lg - g);
+  for (int q = threadIdx.x; q < tasks; q += blockDim.x) {
+    const int c = q & (kc - 1), rem = q >> lgkc;
+    const int j = rem & ((1 << l0) - 1), base = (rem >> l0) << (l0 + g);
+    const int p0 = base + j;
+    T2 x[1 << kGroup];
+#pragma unroll
+    for (int m = 0; m < (1 << kGroup); ++m)
+      if (m < (1 << g)) x[m] = ld(p0 + (m << l0), c);
+    if (DIT) dit_levels<T, INV>(x, g, j, l0, tw, twn);
+    else dif_levels<T, INV>(x, g, j, l0, tw, twn);
+    mid(x, p0, l0, g, c, j);
+#pragma unroll
+    for (int m = 0; m < (1 << kGroup); ++m)
+      if (m < (1 << g)) st(p0 + (m << l0), c, x[m]);
+  }
+}
+
+struct NoMid {
+  template <typename X>
+  __device__ void operator()(X&, int, int, int, int, int) const {}
+};
+
+// LDS access of the column passes.
+template <typename T2>
+struct ColLds {
+  T2* buf;
+  int kc;
+  __device__ T2 operator()(int p, int c) const { return buf[pd(p * kc + c)]; }
+  __device__ void operator()(int p, int c, T2 v) const { buf[pd(p * kc + c)] = v; }
+};
+
+// Global access of the column passes: element p of column c is row
+// (BREV ? bit-reverse of p : p) of the plane, at row stride rs; columns at
+// or past kn (the spectrum's last, narrower chunk) read as zero and are not
+// written.
+template <typename T2, bool BREV>
+struct ColGlobal {
+  T2* base;
+  int64_t rs;
+  int kn, lg;
+  __device__ T2 operator()(int p, int c) const {
+    T2 v;
+    if (c < kn) {
+      v = base[(int64_t)(BREV ? brev(p, lg) : p) * rs + c];
+    } else {
+      v.x = 0; v.y = 0;
+    }
+    return v;
+  }
+  __device__ void operator()(int p, int c, T2 v) const {
+    if (c < kn) base[(int64_t)(BREV ? brev(p, lg) : p) * rs + c] = v;
+  }
+};
+
+// Forward (DIT: bit-reversed rows in, natural rows out) or inverse (DIF:
+// natural rows in, bit-reversed rows out) column transforms, with the top
+// group's values passed through MID before they are stored (the x pass's
+// Green's function and inverse, the power spectrum's shell sums).
+template <typename T, bool INV, typename MID, typename TOPST>
+__device__ __forceinline__ void col_transform(typename Vec<T>::v2* buf, typename Vec<T>::v2* gbase,
+                                              int64_t rs, int kn, int kc, int lg,
+                                              const typename Vec<T>::v2* tw,
+                                              const typename Vec<T>::v2* twl, MID mid,
+                                              TOPST topst) {
+  using T2 = typename Vec<T>::v2;
+  const int ng = 1 << lg, lgkc = __builtin_ctz(kc), ngr = col_groups(lg);
+  const ColLds<T2> lds{buf, kc};
+  if (!INV) {
+    const ColGlobal<T2, true> in{gbase, rs, kn, lg};
+    // the bottom group reads the twiddles from global memory: the barrier
+    // after it is the one that makes the staged copy visible
+    col_group<T, true, false>(kc, lgkc, lg, col_group_levels(lg, 0), tw, ng, in, NoMid{}, lds);
+    __syncthreads();
+    for (int k = 1; k < ngr - 1; ++k) {
+      col_group<T, true, false>(kc, lgkc, lg, col_group_levels(lg, k), twl, ng, lds, NoMid{},
+                                lds);
+      __syncthreads();
+    }
+    col_group<T, true, false>(kc, lgkc, lg, col_group_levels(lg, ngr - 1), twl, ng, lds, mid,
+                              topst);
+  } else {
+    const ColGlobal<T2, false> in{gbase, rs, kn, lg};
+    col_group<T, false, true>(kc, lgkc, lg, col_group_levels(lg, ngr - 1), tw, ng, in, mid,
+                              lds);
+    __syncthreads();
+    for (int k = ngr - 2; k > 0; --k) {
+      col_group<T, false, true>(kc, lgkc, lg, col_group_levels(lg, k), twl, ng, lds, NoMid{},
+                                lds);
+      __syncthreads();
+    }
+    const ColGlobal<T2, true> out{gbase, rs, kn, lg};
+    col_group<T, false, true>(kc, lgkc, lg, col_group_levels(lg, 0), twl, ng, lds, NoMid{}, out);
   }
 }
 
@@ -242,24 +368,18 @@ k_fft_y(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   const int x = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
   T2* plane = spec + (int64_t)x * ng * Ms + kz0;
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    int y = idx / kc, c = idx - y * kc;
-    T2 v;
-    if (c < kn) v = plane[(int64_t)y * Ms + c]; else { v.x = T(0); v.y = T(0); }
-    buf[pd(c * ng + (INV ? y : brev(y, lg)))] = v;
-  }
   const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
-  __syncthreads();
-  if (INV) fft_dif<T, true>(buf, kc, ng, lg, twl, ng);
-  else fft_dit<T, false>(buf, kc, ng, lg, twl, ng);
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    int y = idx / kc, c = idx - y * kc;
-    if (c < kn) plane[(int64_t)y * Ms + c] = buf[pd(c * ng + (INV ? brev(y, lg) : y))];
-  }
+  if (INV)
+    col_transform<T, true>(buf, plane, Ms, kn, kc, lg, tw, twl, NoMid{}, ColLds<T2>{buf, kc});
+  else
+    col_transform<T, false>(buf, plane, Ms, kn, kc, lg, tw, twl, NoMid{},
+                            ColGlobal<T2, false>{plane, Ms, kn, lg});
 }
 
 // Pass 3: forward x transform, Green's function, inverse x transform, for one
-// y-row and a chunk of kc kz-columns.
+// y-row and a chunk of kc kz-columns. The forward transform's top level group
+// ends with the modes in natural order, so the same task multiplies them by
+// G and runs the inverse's top group before they go back to LDS.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
@@ -274,34 +394,34 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   const int kn = min(kc, M1 - kz0);
   const int64_t xs = (int64_t)ng * Ms;
   T2* col = spec + (int64_t)y * Ms + kz0;
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    int x = idx / kc, c = idx - x * kc;
-    T2 v;
-    if (c < kn) v = col[x * xs + c]; else { v.x = T(0); v.y = T(0); }
-    buf[pd(c * ng + brev(x, lg))] = v;
-  }
   const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
-  __syncthreads();
-  fft_dit<T, false>(buf, kc, ng, lg, twl, ng);
   const T ey = etab[y], k2y = k2tab[y];
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    int c = idx >> lg, kx = idx & (ng - 1);
-    int kz = kz0 + c;
-    T g = T(0);
-    if (c < kn) {
-      T k2 = k2tab[kx] + k2y + k2tab[kz];
-      if (k2 > T(0)) g = gconst * etab[kx] * ey * etab[kz] / k2;
+  auto green = [&](T2 (&x)[1 << kGroup], int p0, int l0, int g, int c, int j) {
+    const int kz = kz0 + c;
+#pragma unroll
+    for (int m = 0; m < (1 << kGroup); ++m) {
+      if (m >= (1 << g)) continue;
+      const int kx = p0 + (m << l0);
+      T gk = T(0);
+      if (c < kn) {
+        T k2 = k2tab[kx] + k2y + k2tab[kz];
+        if (k2 > T(0)) gk = gconst * etab[kx] * ey * etab[kz] / k2;
+      }
+      x[m].x *= gk; x[m].y *= gk;
     }
-    T2 v = buf[pd(idx)];
-    v.x *= g; v.y *= g;
-    buf[pd(idx)] = v;
-  }
+    dif_levels<T, true>(x, g, j, l0, twl, ng);
+  };
+  const ColLds<T2> lds{buf, kc};
+  col_transform<T, false>(buf, col, xs, kn, kc, lg, tw, twl, green, lds);
   __syncthreads();
-  fft_dif<T, true>(buf, kc, ng, lg, twl, ng);
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    int x = idx / kc, c = idx - x * kc;
-    if (c < kn) col[x * xs + c] = buf[pd(c * ng + brev(x, lg))];
+  // the inverse below its top group
+  const int lgkc = __builtin_ctz(kc), ngr = col_groups(lg);
+  for (int k = ngr - 2; k > 0; --k) {
+    col_group<T, false, true>(kc, lgkc, lg, col_group_levels(lg, k), twl, ng, lds, NoMid{}, lds);
+    __syncthreads();
   }
+  const ColGlobal<T2, true> out{col, xs, kn, lg};
+  col_group<T, false, true>(kc, lgkc, lg, col_group_levels(lg, 0), twl, ng, lds, NoMid{}, out);
 }
 
 // Power spectrum: forward x transform of one y-row and a chunk of kc
@@ -309,7 +429,8 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
 // divided by W(k)^2 when deconvolving, is added with its full-space
 // multiplicity (1 on the kz = 0 and Nyquist planes, else 2) into its shell
 // b = floor(|n| - 1/2): acc = [power sums | |n| sums | mode counts][nbins],
-// then the top-hat-weighted sum for sigma and rho_0 (the k = 0 value).
+// then the top-hat-weighted sum for sigma and rho_0 (the k = 0 value). The
+// modes are summed straight from the forward transform's top level group.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
@@ -324,28 +445,20 @@ k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int 
   const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
   const int64_t xs = (int64_t)ng * Ms;
-  const T2* col = spec + (int64_t)y * Ms + kz0;
+  // (read only: the transform's global stores go to LDS or to the sums)
+  T2* col = const_cast<T2*>(spec) + (int64_t)y * Ms + kz0;
   for (int i = threadIdx.x; i < 3 * nbins + 1; i += kThreads) hist[i] = 0.0;
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    int x = idx / kc, c = idx - x * kc;
-    T2 v;
-    if (c < kn) v = col[x * xs + c]; else { v.x = T(0); v.y = T(0); }
-    buf[pd(c * ng + brev(x, lg))] = v;
-  }
   const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
-  __syncthreads();
-  fft_dit<T, false>(buf, kc, ng, lg, twl, ng);     // ends with a barrier
   const int half = ng >> 1;
   const int ny = y < half ? y : y - ng;
-  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
-    const int c = idx >> lg, kx = idx & (ng - 1), kz = kz0 + c;
-    if (c >= kn) continue;
+  auto shells = [&](int kx, int c, T2 v) {
+    const int kz = kz0 + c;
+    if (c >= kn) return;
     const int nx = kx < half ? kx : kx - ng;
-    const T2 v = buf[pd(idx)];
     const int n2 = nx * nx + ny * ny + kz * kz;
     if (n2 == 0) {
       acc[3 * nbins + 1] = (double)v.x;             // rho_0: one thread of one block
-      continue;
+      return;
     }
     double pw = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     if (deconv) {
@@ -378,11 +491,15 @@ k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int 
       wt = 3.0 * (sx - x * cx) / (x * x * x);
     }
     atomicAdd(&hist[3 * nbins], mult * pw * wt * wt);
-  }
+  };
+  // (the histogram's clearing is ordered before the sums by the transform's
+  // barriers)
+  col_transform<T, false>(buf, col, xs, kn, kc, lg, tw, twl, NoMid{}, shells);
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * nbins + 1; i += kThreads)
     if (hist[i] != 0.0) atomicAdd(&acc[i], hist[i]);
 }
+
 
 // Shell averages and sigma from the accumulated sums.
 __global__ void __launch_bounds__(256)
