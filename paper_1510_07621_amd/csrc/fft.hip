@@ -118,35 +118,38 @@ __device__ __forceinline__ void dif_levels(typename Vec<T>::v2 (&x)[1 << kGroup]
   }
 }
 
-// nb independent length-len transforms in buf (contiguous, buf[b*len + i]),
-// all levels through LDS (the z passes).
-template <typename T, bool DIT, bool INV>
-__device__ void fft_lines(typename Vec<T>::v2* buf, int nb, int len, int lglen,
-                          const typename Vec<T>::v2* __restrict__ tw, int twn) {
+// One level group (levels l0 .. l0 + g - 1) of nb transforms of length
+// len = 2^lglen held line by line (element i of line b at p = b len + i):
+// LD(p) gives element p, ST(p, v) takes it back. The z passes.
+template <typename T, bool DIT, bool INV, typename LD, typename ST>
+__device__ __forceinline__ void line_group(int nb, int len, int lglen, int l0, int g,
+                                           const typename Vec<T>::v2* tw, int twn, LD ld,
+                                           ST st) {
   using T2 = typename Vec<T>::v2;
-  for (int k = 0; k < lglen; k += kGroup) {
-    // DIT: levels from the bottom up; DIF: from the top down
-    const int g = min(kGroup, lglen - k);
-    const int l0 = DIT ? k : lglen - k - g;
-    const int tasks = len >> g;                 // per transform
-    const int lgt = lglen - g;
-    for (int q = threadIdx.x; q < nb * tasks; q += blockDim.x) {
-      const int bi = q >> lgt, rem = q & (tasks - 1);
-      const int j = rem & ((1 << l0) - 1), base = (rem >> l0) << (l0 + g);
-      const int p0 = bi * len + base + j;
-      T2 x[1 << kGroup];
+  const int tasks = len >> g;                 // per transform
+  const int lgt = lglen - g;
+  for (int q = threadIdx.x; q < nb * tasks; q += blockDim.x) {
+    const int bi = q >> lgt, rem = q & (tasks - 1);
+    const int j = rem & ((1 << l0) - 1), base = (rem >> l0) << (l0 + g);
+    const int p0 = bi * len + base + j;
+    T2 x[1 << kGroup];
 #pragma unroll
-      for (int m = 0; m < (1 << kGroup); ++m)
-        if (m < (1 << g)) x[m] = buf[pd(p0 + (m << l0))];
-      if (DIT) dit_levels<T, INV>(x, g, j, l0, tw, twn);
-      else dif_levels<T, INV>(x, g, j, l0, tw, twn);
+    for (int m = 0; m < (1 << kGroup); ++m)
+      if (m < (1 << g)) x[m] = ld(p0 + (m << l0));
+    if (DIT) dit_levels<T, INV>(x, g, j, l0, tw, twn);
+    else dif_levels<T, INV>(x, g, j, l0, tw, twn);
 #pragma unroll
-      for (int m = 0; m < (1 << kGroup); ++m)
-        if (m < (1 << g)) buf[pd(p0 + (m << l0))] = x[m];
-    }
-    __syncthreads();
+    for (int m = 0; m < (1 << kGroup); ++m)
+      if (m < (1 << g)) st(p0 + (m << l0), x[m]);
   }
 }
+
+template <typename T2>
+struct LineLds {
+  T2* buf;
+  __device__ T2 operator()(int p) const { return buf[pd(p)]; }
+  __device__ void operator()(int p, T2 v) const { buf[pd(p)] = v; }
+};
 
 // Pass 1: real z-lines -> half spectra. lines per block = nl.
 template <typename T>
@@ -160,13 +163,20 @@ k_fft_z_r2c(const T* __restrict__ grid, typename Vec<T>::v2* __restrict__ spec, 
   const int64_t line0 = (int64_t)blockIdx.x * nl;
   const int Ms = spec_stride(ng);
   const T2* in = reinterpret_cast<const T2*>(grid);
-  for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
-    int b = idx >> lgM, m = idx & (M - 1);
-    buf[pd(b * M + brev(m, lgM))] = in[(line0 + b) * M + m];
-  }
   const T2* twl = stage_twiddles(buf, nl * M, tw, ng);
+  const LineLds<T2> lds{buf};
+  // DIT, levels from the bottom up; the first group reads its (bit-reversed)
+  // inputs straight from global memory, with the twiddles from there too
+  auto gin = [&](int p) {
+    const int b = p >> lgM, i = p & (M - 1);
+    return in[(line0 + b) * M + brev(i, lgM)];
+  };
+  line_group<T, true, false>(nl, M, lgM, 0, min(kGroup, lgM), tw, ng, gin, lds);
   __syncthreads();
-  fft_lines<T, true, false>(buf, nl, M, lgM, twl, ng);
+  for (int l0 = kGroup; l0 < lgM; l0 += kGroup) {
+    line_group<T, true, false>(nl, M, lgM, l0, min(kGroup, lgM - l0), twl, ng, lds, lds);
+    __syncthreads();
+  }
   const int M1 = M + 1;
   for (int idx = threadIdx.x; idx < nl * M1; idx += kThreads) {
     int b = idx / M1, k = idx - b * M1;
@@ -213,11 +223,22 @@ k_fft_z_c2r(const typename Vec<T>::v2* __restrict__ spec, T* __restrict__ grid, 
   }
   const T2* twl = stage_twiddles(buf, nl * M, tw, ng);
   __syncthreads();
-  fft_lines<T, false, true>(buf, nl, M, lgM, twl, ng);
+  // DIF, levels from the top down; the last group stores its (bit-reversed)
+  // outputs straight to global memory
   T2* out = reinterpret_cast<T2*>(grid);
-  for (int idx = threadIdx.x; idx < nl * M; idx += kThreads) {
-    int b = idx >> lgM, m = idx & (M - 1);
-    out[(line0 + b) * M + m] = buf[pd(b * M + brev(m, lgM))];
+  auto gout = [&](int p, T2 v) {
+    const int b = p >> lgM, i = p & (M - 1);
+    out[(line0 + b) * M + brev(i, lgM)] = v;
+  };
+  const LineLds<T2> lds{buf};
+  for (int k = 0; k < lgM; k += kGroup) {
+    const int g = min(kGroup, lgM - k), l0 = lgM - k - g;
+    if (l0 > 0) {
+      line_group<T, false, true>(nl, M, lgM, l0, g, twl, ng, lds, lds);
+      __syncthreads();
+    } else {
+      line_group<T, false, true>(nl, M, lgM, l0, g, twl, ng, lds, gout);
+    }
   }
 }
 
