@@ -260,6 +260,17 @@ __device__ __forceinline__ int low_group(int lg) {
   return r ? r : kGroup;
 }
 
+// Work item of a column-pass block. Workgroups go to the 8 XCDs in turn
+// (block b to XCD b mod 8), each XCD with its own L2, and two neighbouring
+// chunks of a row share cache lines (an FP32 chunk of 8 columns is half a
+// 128-byte line); so items 2i and 2i + 1 run as blocks 16s + r and
+// 16s + r + 8, on one XCD one after the other. The block count is a multiple
+// of 16 (ng is).
+__device__ __forceinline__ int col_item() {
+  const int b = blockIdx.x, r = b & 15;
+  return (b & ~15) + 2 * (r & 7) + (r >> 3);
+}
+
 struct ColGroup {
   int l0, g;
 };
@@ -386,7 +397,8 @@ k_fft_y(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   T2* buf = reinterpret_cast<T2*>(smem_raw);
   const int M1 = (ng >> 1) + 1, Ms = spec_stride(ng);
   const int nchunk = (M1 + kc - 1) / kc;
-  const int x = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
+  const int item = col_item();
+  const int x = item / nchunk, kz0 = (item % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
   T2* plane = spec + (int64_t)x * ng * Ms + kz0;
   const T2* twl = stage_twiddles(buf, kc * ng, tw, ng);
@@ -411,7 +423,8 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
   T2* buf = reinterpret_cast<T2*>(smem_raw);
   const int M1 = (ng >> 1) + 1, Ms = spec_stride(ng);
   const int nchunk = (M1 + kc - 1) / kc;
-  const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
+  const int item = col_item();
+  const int y = item / nchunk, kz0 = (item % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
   const int64_t xs = (int64_t)ng * Ms;
   T2* col = spec + (int64_t)y * Ms + kz0;
@@ -463,7 +476,8 @@ k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int 
   __shared__ double hist[3 * kMaxPowerBins + 1];
   const int M1 = (ng >> 1) + 1, Ms = spec_stride(ng);
   const int nchunk = (M1 + kc - 1) / kc;
-  const int y = blockIdx.x / nchunk, kz0 = (blockIdx.x % nchunk) * kc;
+  const int item = col_item();
+  const int y = item / nchunk, kz0 = (item % nchunk) * kc;
   const int kn = min(kc, M1 - kz0);
   const int64_t xs = (int64_t)ng * Ms;
   // (read only: the transform's global stores go to LDS or to the sums)
