@@ -99,29 +99,47 @@ def plan_for(binding, w, precision, pair_partials=0, adjoint=False):
                                        adjoint=adjoint), w.n)
 
 
-def run_steps(binding, plan, x, p, F, m, dt, box, steps):
-    """KDK steps; F holds the force at x on entry and on exit."""
+def run_steps(binding, plan, st, m, dt, box, steps):
+    """KDK steps on the state st (x, p, F, ids, order, and spare buffers x2,
+    p2, ids2); F holds the force at x on entry and on exit. The particles are
+    kept in the cell order of each force call: the force comes in that order
+    and the second half-kick moves positions, momenta and ids into it, so the
+    next binning reads nearly sorted input and the force's stores are in
+    order."""
     for _ in range(steps):
-        binding.kick_drift(x, p, F, m, 0.5 * dt, dt, box)    # kick, then drift, one pass
-        plan.force(x, m, out=F)
-        binding.kick(p, F, 0.5 * dt)
+        binding.kick_drift(st["x"], st["p"], st["F"], m, 0.5 * dt, dt, box)   # one pass
+        plan.force_cell_order(st["x"], m, out=st["F"], order=st["order"])
+        binding.kick_reorder(st["order"], st["x"], st["p"], st["F"], 0.5 * dt, ids=st["ids"],
+                             out=(st["x2"], st["p2"], st["ids2"], None))
+        for k in ("x", "p", "ids"):
+            st[k], st[k + "2"] = st[k + "2"], st[k]
 
 
 def time_steps(binding, torch, w, pos0, precision, steps, warmup, dt, pair_partials):
     plan = plan_for(binding, w, precision, pair_partials)
     x = torch.as_tensor(pos0, device="cuda").contiguous()
-    p = torch.zeros_like(x)
-    F = torch.empty_like(x)
+    st = {"x": x, "p": torch.zeros_like(x), "F": torch.empty_like(x),
+          "ids": torch.arange(w.n, dtype=torch.int64, device="cuda"),
+          "order": torch.empty(w.n, dtype=torch.int32, device="cuda"),
+          "x2": torch.empty_like(x), "p2": torch.empty_like(x),
+          "ids2": torch.empty(w.n, dtype=torch.int64, device="cuda")}
     m = w.mass
-    plan.force(x, m, out=F)
-    run_steps(binding, plan, x, p, F, m, dt, w.box, warmup)
+    # the initial force, and the particles into its cell order
+    plan.force_cell_order(st["x"], m, out=st["F"], order=st["order"])
+    binding.kick_reorder(st["order"], st["x"], st["p"], st["F"], 0.0, ids=st["ids"],
+                         out=(st["x2"], st["p2"], st["ids2"], None))
+    for k in ("x", "p", "ids"):
+        st[k], st[k + "2"] = st[k + "2"], st[k]
+    run_steps(binding, plan, st, m, dt, w.box, warmup)
+    x = st["x"]
     pairs_before = plan.pair_count(x)
     torch.cuda.synchronize()
     plan.set_timing(steps)
     t0 = time.perf_counter()
-    run_steps(binding, plan, x, p, F, m, dt, w.box, steps)
+    run_steps(binding, plan, st, m, dt, w.box, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    x = st["x"]
     calls, stage_ms = plan.stage_times()
     plan.set_timing(0)
     pairs_after = plan.pair_count(x)
@@ -453,6 +471,7 @@ def main():
                                "leapfrog step (dt=%g) per step" % args.dt,
             "n_particles": w.n, "grid_n": w.grid_n, "precision": "fp32 force, fp64 x/p",
             "pair_partials": partials,
+            "particle_order": "cell order of the last force call (ids carried along)",
         },
         "pair_interactions_per_s": pairs / (pair_ms * 1e-3),
         "pairs_per_step": pairs,

@@ -122,12 +122,15 @@ int p3m_plan_set_stream(p3m_plan* plan, void* hip_stream);
 
 /* Full P3M force (PP + PM) on n particles. After binning on the plan's
  * stream, the mesh part (deposit, Poisson solve) runs on a second stream of
- * the plan (default priority) beside the pair sum, which writes the force;
- * the plan's stream then waits for it and the interpolation adds the mesh
+ * the plan (default priority) beside the pair sum, which writes its sorted
+ * acceleration; the plan's stream then waits for it and the interpolation
+ * adds the mesh force and writes the force. With the one-sided pair sum
+ * (pair_partials > 0) the interpolation runs on the second stream too and
+ * the gather of the reactions, after the pair sum, adds it and writes the
  * force. To the caller all of it is ordered on the plan's stream, as one
- * call. Stage timers of deposit and FFT are recorded on the second stream,
- * so they include the time those kernels wait for compute units held by
- * the pair sum.
+ * call. Stage timers of deposit, FFT and (one-sided) interpolation are
+ * recorded on the second stream, so they include the time those kernels
+ * wait for compute units held by the pair sum.
  *   pos         device, double [3][n], components in [0, box)
  *   mass        device, double [n], or NULL to give every particle mass_scalar
  *               (one mass per particle group, guide Ch. 6)
@@ -136,6 +139,21 @@ int p3m_plan_set_stream(p3m_plan* plan, void* hip_stream);
  * n == 0 is a successful no-op. */
 int p3m_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
               double mass_scalar, void* force, int32_t force_fp32);
+
+/* The force of p3m_force written in the cell order of this call's binning
+ * rather than the input order, together with that order: force[.][s] is the
+ * force on input particle order_out[s]. The order sorts the particles by PM
+ * cell (cell index (cx ng + cy) ng + cz); inside a cell it can differ from
+ * call to call. A caller that keeps its particles in this order (see
+ * p3m_kick_reorder) hands the next call input that is nearly sorted already
+ * (particles move little between steps), so the binning and the force's
+ * stores touch memory in order instead of scattering. Same computation and
+ * arguments as p3m_force; order_out: device int32 [n], overwritten, not
+ * overlapping pos, mass or force (EINVAL). Guide Ch. 1 and Ch. 5 as for
+ * p3m_force. */
+int p3m_force_cell_order(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
+                         double mass_scalar, void* force, int32_t force_fp32,
+                         int32_t* order_out);
 
 /* Long-range (PM) part only: F_i = m_i a_PM(x_i). Same arguments. */
 int pm_force(p3m_plan* plan, int64_t n, const double* pos, const double* mass,
@@ -239,6 +257,28 @@ int p3m_pair_count(p3m_plan* plan, int64_t n, const double* pos,
  * force_fp32 != 0 else double. */
 int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32,
              double c_kick, void* hip_stream);
+
+/* Kick and reorder (guide Ch. 5 kick_algorithms): the second half-kick of
+ * a kick-drift-kick step for a caller that keeps its particles in the cell
+ * order of the last force call. With i = order[s]:
+ *   mom_out[.][s] = mom[.][i] + c_kick * force[.][s]   (force in cell order,
+ *                                                      as p3m_force_cell_order
+ *                                                      writes it)
+ *   pos_out[.][s] = pos[.][i], ids_out[s] = ids[i], mass_out[s] = mass[i]
+ * Each sum and product is one IEEE double operation, as in p3m_kick, so the
+ * momenta equal p3m_kick's followed by the permutation bit for bit.
+ *   order       device int32 [n], a permutation of 0 .. n-1 (entries out of
+ *               range are clamped into it: wrong values, no fault)
+ *   pos, mom    device double [3][n]; force device [3][n], float if
+ *               force_fp32 != 0 else double
+ *   ids, mass   device int64 [n] / double [n] carried along, or NULL (then
+ *               ids_out / mass_out NULL too, else EINVAL)
+ *   outputs     device, the shapes of the inputs; no output may overlap an
+ *               input or another output (EINVAL) */
+int p3m_kick_reorder(int64_t n, const int32_t* order, const double* pos, const double* mom,
+                     const void* force, int32_t force_fp32, const int64_t* ids,
+                     const double* mass, double c_kick, double* pos_out, double* mom_out,
+                     int64_t* ids_out, double* mass_out, void* hip_stream);
 
 /* Drift (guide Ch. 8 drift test: comoving motion, crossing box faces):
  * x <- wrap(x + c_drift * (p / m)), wrap(y) = y - box*floor(y/box) and a

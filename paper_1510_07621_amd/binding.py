@@ -73,6 +73,9 @@ def _load():
         "pp_force_vjp": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, vp]),
         "p3m_drift_vjp": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, vp]),
         "p3m_kick": (ctypes.c_int, [i64, vp, vp, i32, dbl, vp]),
+        "p3m_force_cell_order": (ctypes.c_int, [vp, i64, vp, vp, dbl, vp, i32, vp]),
+        "p3m_kick_reorder": (ctypes.c_int, [i64, vp, vp, vp, vp, i32, vp, vp, dbl, vp, vp, vp,
+                                            vp, vp]),
         "p3m_kick_drift": (ctypes.c_int, [i64, vp, vp, vp, i32, vp, dbl, dbl, dbl, dbl, vp]),
         "p3m_drift": (ctypes.c_int, [i64, vp, vp, vp, dbl, dbl, dbl, vp]),
         "p3m_set_timing": (ctypes.c_int, [vp, i32]),
@@ -346,6 +349,19 @@ class Plan:
         """Full P3M force F = m (a_PP + a_PM), shape (3, n)."""
         return self._force(_lib.p3m_force, "p3m_force", pos, mass, out, fp32_out)
 
+    def force_cell_order(self, pos, mass=None, out=None, order=None, fp32_out=False):
+        """The P3M force in the cell order of this call's binning: returns
+        (F, order) with F[:, s] the force on input particle order[s]."""
+        n = _vec3(pos, "pos")
+        if order is None:
+            order = torch.empty(n, dtype=torch.int32, device=pos.device)
+        elif order.dtype != torch.int32 or order.shape != (n,) or not order.is_contiguous():
+            raise ValueError("order must be a contiguous int32 tensor of n entries")
+
+        def fn(h, n_, p, m, ms, f, f32):
+            return _lib.p3m_force_cell_order(h, n_, p, m, ms, f, f32, _ptr(order))
+        return self._force(fn, "p3m_force_cell_order", pos, mass, out, fp32_out), order
+
     def pm_force(self, pos, mass=None, out=None, fp32_out=False):
         return self._force(_lib.pm_force, "pm_force", pos, mass, out, fp32_out)
 
@@ -431,6 +447,46 @@ def kick(mom: torch.Tensor, force: torch.Tensor, c_kick: float) -> torch.Tensor:
     _check(_lib.p3m_kick(n, _ptr(mom), _ptr(force), 1 if force.dtype == torch.float32 else 0,
                          float(c_kick), _stream_ptr()), "p3m_kick")
     return mom
+
+
+def kick_reorder(order: torch.Tensor, pos: torch.Tensor, mom: torch.Tensor,
+                 force: torch.Tensor, c_kick: float, ids=None, mass=None, out=None):
+    """Second half-kick of a step in cell order: with i = order[s],
+    mom_out[:, s] = mom[:, i] + c_kick force[:, s] and pos_out[:, s] =
+    pos[:, i] (ids and a per-particle mass array carried along). `force` is
+    in cell order (Plan.force_cell_order). Returns (pos_out, mom_out,
+    ids_out, mass_out); `out` may give those buffers (None entries are
+    allocated)."""
+    n = _vec3(pos, "pos")
+    if mass is not None and not isinstance(mass, torch.Tensor):
+        mass = None                      # a scalar mass needs no reordering
+    if _vec3(mom, "mom") != n:
+        raise ValueError("mom must match pos")
+    if _vec3(force, "force", force.dtype) != n or force.dtype not in (torch.float32,
+                                                                       torch.float64):
+        raise ValueError("force must be (3, n) float32 or float64")
+    if order.dtype != torch.int32 or order.shape != (n,) or not order.is_contiguous():
+        raise ValueError("order must be a contiguous int32 tensor of n entries")
+    for name, t, dt in (("ids", ids, torch.int64), ("mass", mass, torch.float64)):
+        if t is not None and (t.dtype != dt or t.shape != (n,) or not t.is_contiguous()
+                              or t.device != pos.device):
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor of n entries")
+    po, mo, io, ma = out if out is not None else (None, None, None, None)
+    po = torch.empty_like(pos) if po is None else po
+    mo = torch.empty_like(mom) if mo is None else mo
+    if ids is not None and io is None:
+        io = torch.empty_like(ids)
+    if mass is not None and ma is None:
+        ma = torch.empty_like(mass)
+    if _vec3(po, "pos_out") != n or _vec3(mo, "mom_out") != n:
+        raise ValueError("pos_out and mom_out must be (3, n) float64")
+    _check(_lib.p3m_kick_reorder(n, _ptr(order), _ptr(pos), _ptr(mom), _ptr(force),
+                                 1 if force.dtype == torch.float32 else 0, _ptr(ids), _ptr(mass),
+                                 float(c_kick), _ptr(po), _ptr(mo),
+                                 _ptr(io) if ids is not None else None,
+                                 _ptr(ma) if mass is not None else None, _stream_ptr()),
+           "p3m_kick_reorder")
+    return po, mo, io, ma
 
 
 def kick_drift(pos: torch.Tensor, mom: torch.Tensor, force: torch.Tensor, mass,

@@ -35,17 +35,41 @@ __device__ __forceinline__ int cell_coord(double t, int ng) {
   return (int)t;
 }
 
-__global__ void k_bin_count(int64_t n, const double* __restrict__ pos, int ng, int lg,
-                            double inv_h, int32_t* __restrict__ key,
-                            int32_t* __restrict__ rank, int32_t* __restrict__ count) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int cx = cell_coord(pos[i] * inv_h, ng);
-  int cy = cell_coord(pos[n + i] * inv_h, ng);
-  int cz = cell_coord(pos[2 * n + i] * inv_h, ng);
-  int c = (((cx << lg) | cy) << lg) | cz;
-  key[i] = c;
-  rank[i] = atomicAdd(&count[c], 1);
+// Consecutive lanes of a wave in the same cell (input already in cell order,
+// as a caller that keeps its particles in the order of the last binning
+// hands it) share one atomic: the run's first lane adds the run's length
+// and each lane's rank is the old count plus its place in the run. With
+// input in random order every lane is a run of one.
+__global__ void __launch_bounds__(256)
+k_bin_count(int64_t n, const double* __restrict__ pos, int ng, int lg, double inv_h,
+            int32_t* __restrict__ key, int32_t* __restrict__ rank,
+            int32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  int c = -1;
+  if (valid) {
+    int cx = cell_coord(pos[i] * inv_h, ng);
+    int cy = cell_coord(pos[n + i] * inv_h, ng);
+    int cz = cell_coord(pos[2 * n + i] * inv_h, ng);
+    c = (((cx << lg) | cy) << lg) | cz;
+    key[i] = c;
+  }
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(c, 1, 64);
+  const bool head = valid && (lane == 0 || prev != c);
+  const unsigned long long heads = __ballot(head);
+  // runs end at the next head or at the first lane past n
+  const unsigned long long bounds = heads | ~__ballot(valid);
+  const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1;
+  const int start = valid ? 63 - __builtin_clzll(heads & upto) : lane;
+  int base = 0;
+  if (head) {
+    const unsigned long long above = lane == 63 ? 0ull : bounds >> (lane + 1);
+    const int len = above ? __builtin_ctzll(above) + 1 : 64 - lane;
+    base = atomicAdd(&count[c], len);
+  }
+  base = __shfl(base, start, 64);
+  if (valid) rank[i] = base + (lane - start);
 }
 
 template <typename T>

@@ -209,7 +209,7 @@ k_interp(const typename Vec<T>::v4* __restrict__ rec, const int32_t* __restrict_
       o.x = -ax; o.y = -ay; o.z = -az; o.w = T(0);
       acc_out[s] = o;
     } else {
-      int64_t i = perm[s];
+      int64_t i = perm ? perm[s] : s;      // (no permutation: cell order)
       double m = (double)p.w;
       // acc_pp: the pair sum's sorted acceleration, added here (the P3M call
       // whose mesh part ran beside the pair sum)
@@ -265,7 +265,7 @@ hipError_t launch_interp_bricks(p3m_plan* P, int64_t n, void* force_out, int for
   typename Vec<T>::v4* acc = (typename Vec<T>::v4*)sorted_out;
   k_interp<T, BX, BZ><<<nb, kThreads, 0, P->stream>>>(
       (const typename Vec<T>::v4*)W.rec, W.skey, W.start, P->ng, P->lg, T(1.0 / P->h),
-      (const T*)W.grid, c1, c2, acc, W.perm, n, force_out, force_fp32,
+      (const T*)W.grid, c1, c2, acc, P->cell_order ? nullptr : W.perm, n, force_out, force_fp32,
       (const typename Vec<T>::v4*)acc_pp);
   return hipGetLastError();
 }

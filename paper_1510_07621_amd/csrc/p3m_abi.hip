@@ -875,6 +875,29 @@ int p3m_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
   return force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kP3M);
 }
 
+int p3m_force_cell_order(p3m_plan* P, int64_t n, const double* pos, const double* mass,
+                         double mass_scalar, void* force, int32_t force_fp32,
+                         int32_t* order_out) {
+  if (!P || n < 0 || n > P->n_max) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!order_out) return P3M_EINVAL;
+  const size_t obytes = (size_t)n * sizeof(int32_t);
+  const size_t fbytes = (size_t)(3 * n) * (force_fp32 ? sizeof(float) : sizeof(double));
+  if (overlaps(order_out, obytes, pos, (size_t)(3 * n) * sizeof(double)) ||
+      overlaps(order_out, obytes, mass, (size_t)n * sizeof(double)) ||
+      overlaps(order_out, obytes, force, fbytes))
+    return P3M_EINVAL;
+  struct CellOrder {   // the force's final stores skip the permutation for this call
+    p3m_plan* P;
+    explicit CellOrder(p3m_plan* p) : P(p) { P->cell_order = true; }
+    ~CellOrder() { P->cell_order = false; }
+  } on(P);
+  const int st = force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kP3M);
+  if (st != P3M_OK) return st;
+  return status_of(hipMemcpyAsync(order_out, P->ws.perm, obytes, hipMemcpyDeviceToDevice,
+                                  P->stream));
+}
+
 int pm_force(p3m_plan* P, int64_t n, const double* pos, const double* mass,
              double mass_scalar, void* force, int32_t force_fp32) {
   return force_entry(P, n, pos, mass, mass_scalar, force, force_fp32, Part::kPM);
@@ -976,6 +999,33 @@ int p3m_kick(int64_t n, double* mom, const void* force, int32_t force_fp32, doub
   if (!mom || !force || !std::isfinite(c_kick)) return P3M_EINVAL;
   return status_of(launch_kick(n, mom, force, force_fp32 ? 1 : 0, c_kick,
                                (hipStream_t)hip_stream));
+}
+
+int p3m_kick_reorder(int64_t n, const int32_t* order, const double* pos, const double* mom,
+                     const void* force, int32_t force_fp32, const int64_t* ids,
+                     const double* mass, double c_kick, double* pos_out, double* mom_out,
+                     int64_t* ids_out, double* mass_out, void* hip_stream) {
+  if (n < 0) return P3M_EINVAL;
+  if (n == 0) return P3M_OK;
+  if (!order || !pos || !mom || !force || !pos_out || !mom_out || !std::isfinite(c_kick))
+    return P3M_EINVAL;
+  if ((ids == nullptr) != (ids_out == nullptr) || (mass == nullptr) != (mass_out == nullptr))
+    return P3M_EINVAL;
+  const size_t vb = (size_t)(3 * n) * sizeof(double), sb8 = (size_t)n * 8;
+  const size_t fb = (size_t)(3 * n) * (force_fp32 ? sizeof(float) : sizeof(double));
+  const void* in[] = {order, pos, mom, force, ids, mass};
+  const size_t inb[] = {(size_t)n * sizeof(int32_t), vb, vb, fb, sb8, sb8};
+  void* out[] = {pos_out, mom_out, ids_out, mass_out};
+  const size_t outb[] = {vb, vb, sb8, sb8};
+  for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 6; ++b)
+      if (overlaps(out[a], outb[a], in[b], inb[b])) return P3M_EINVAL;
+    for (int b = a + 1; b < 4; ++b)
+      if (overlaps(out[a], outb[a], out[b], outb[b])) return P3M_EINVAL;
+  }
+  return status_of(launch_kick_reorder(n, order, pos, mom, force, force_fp32 ? 1 : 0, ids, mass,
+                                       c_kick, pos_out, mom_out, ids_out, mass_out,
+                                       (hipStream_t)hip_stream));
 }
 
 int p3m_drift(int64_t n, double* pos, const double* mom, const double* mass,

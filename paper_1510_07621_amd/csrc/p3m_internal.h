@@ -111,6 +111,9 @@ struct p3m_plan {
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
+  // set for the duration of a p3m_force_cell_order call: the force is
+  // written at the particle's sorted slot instead of its input index
+  bool cell_order = false;
   // geometry
   int ng = 0, lg = 0;           // grid cells per side and its log2
   int64_t ncell = 0;
@@ -209,6 +212,11 @@ hipError_t launch_kick_drift(int64_t n, double* pos, double* mom, const void* fo
                              hipStream_t s);
 hipError_t launch_kick(int64_t n, double* mom, const void* force, int fp32, double c,
                        hipStream_t s);
+hipError_t launch_kick_reorder(int64_t n, const int32_t* order, const double* pos,
+                               const double* mom, const void* force, int fp32,
+                               const int64_t* ids, const double* mass, double c,
+                               double* pos_out, double* mom_out, int64_t* ids_out,
+                               double* mass_out, hipStream_t s);
 hipError_t launch_drift(int64_t n, double* pos, const double* mom, const double* mass,
                         double ms, double c, double box, hipStream_t s);
 

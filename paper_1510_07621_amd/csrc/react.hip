@@ -346,7 +346,7 @@ k_react_gather(GatherArgs<T> A) {
     A.acc_out[s] = o;
     return;
   }
-  const int64_t i = A.perm[s];
+  const int64_t i = A.perm ? A.perm[s] : s;   // (no permutation: cell order)
   const double m = (double)rs.w;
   if (A.out_fp32) {
     float* F = (float*)A.out;
@@ -412,7 +412,7 @@ hipError_t launch_react_gather(p3m_plan* P, int64_t n, double rscale, bool unifo
   A.acc = (const typename Vec<T>::v4*)W.acc_pm;
   A.add = (const typename Vec<T>::v4*)acc_add;
   A.acc_out = (typename Vec<T>::v4*)acc_out;
-  A.perm = W.perm;
+  A.perm = P->cell_order ? nullptr : W.perm;
   A.out = out;
   A.out_fp32 = out_fp32;
   if (uniform_mass)

@@ -62,7 +62,50 @@ __global__ void k_kick_drift(int64_t n, double* __restrict__ pos, double* __rest
   pos[k] = (w >= box) ? 0.0 : w;
 }
 
+// Kick and reorder: component k = d n + s of the outputs takes particle
+// i = order[s] of the inputs; the momentum's sum is k_kick's operation.
+template <typename F>
+__global__ void k_kick_reorder(int64_t n, const int32_t* __restrict__ order,
+                               const double* __restrict__ pos, const double* __restrict__ mom,
+                               const F* __restrict__ force, const int64_t* __restrict__ ids,
+                               const double* __restrict__ mass, double c,
+                               double* __restrict__ pos_out, double* __restrict__ mom_out,
+                               int64_t* __restrict__ ids_out, double* __restrict__ mass_out) {
+#pragma clang fp contract(off)
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * n) return;
+  const int64_t d = k / n, s = k - d * n;
+  // (clamped: an order that is not a permutation gives wrong values, never
+  // an access outside the arrays)
+  const int64_t o = min(max((int64_t)order[s], (int64_t)0), n - 1);
+  const int64_t i = d * n + o;
+  double f = (double)force[k];
+  mom_out[k] = mom[i] + c * f;
+  pos_out[k] = pos[i];
+  if (d == 0) {
+    if (ids) ids_out[s] = ids[o];
+    if (mass) mass_out[s] = mass[o];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_kick_reorder(int64_t n, const int32_t* order, const double* pos,
+                               const double* mom, const void* force, int fp32,
+                               const int64_t* ids, const double* mass, double c,
+                               double* pos_out, double* mom_out, int64_t* ids_out,
+                               double* mass_out, hipStream_t s) {
+  unsigned blocks = (unsigned)((3 * n + kThreads - 1) / kThreads);
+  if (fp32)
+    k_kick_reorder<float><<<blocks, kThreads, 0, s>>>(n, order, pos, mom, (const float*)force,
+                                                      ids, mass, c, pos_out, mom_out, ids_out,
+                                                      mass_out);
+  else
+    k_kick_reorder<double><<<blocks, kThreads, 0, s>>>(n, order, pos, mom,
+                                                       (const double*)force, ids, mass, c,
+                                                       pos_out, mom_out, ids_out, mass_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_kick_drift(int64_t n, double* pos, double* mom, const void* force, int fp32,
                              const double* mass, double ms, double ck, double cd, double box,

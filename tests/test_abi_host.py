@@ -106,6 +106,21 @@ def test_calls_on_null_plan_and_bad_arguments(b):
     assert L.p3m_ewald_correction(None, 10, 1, 2) == -1
     for fn in (L.p3m_force_vjp, L.pm_force_vjp, L.pp_force_vjp):
         assert fn(None, 10, 1, None, 1.0, 2, 3) == -1
+    assert L.p3m_force_cell_order(None, 10, 1, None, 1.0, 2, 0, 3) == -1
+    # kick and reorder: order, pos, mom, force, ids, mass, c, outputs ...
+    KR = L.p3m_kick_reorder
+    big = 1 << 20                                    # (addresses only, never touched)
+    assert KR(-1, 1, 2, 3, 4, 0, None, None, 1.0, 5, 6, None, None, None) == -1
+    assert KR(0, None, None, None, None, 0, None, None, 1.0, None, None, None, None,
+              None) == 0                                              # empty: no-op
+    assert KR(5, None, 2, 3, 4, 0, None, None, 1.0, 5, 6, None, None, None) == -1  # no order
+    assert KR(5, 1, 2, 3, 4, 0, None, None, float("nan"), 5, 6, None, None, None) == -1
+    assert KR(5, 1, 2, 3, 4, 0, 7, None, 1.0, 5, 6, None, None, None) == -1  # ids w/o ids_out
+    assert KR(5, 1, 2, 3, 4, 0, None, 8, 1.0, 5, 6, None, None, None) == -1  # mass w/o out
+    assert KR(5, big, 2 * big, 3 * big, 4 * big, 0, None, None, 1.0, 2 * big, 6 * big, None,
+              None, None) == -1                                      # pos_out over pos
+    assert KR(5, big, 2 * big, 3 * big, 4 * big, 0, None, None, 1.0, 5 * big, 5 * big + 8,
+              None, None, None) == -1                                # outputs overlap
     assert L.p3m_drift_vjp(-1, 1, 2, None, 1.0, 1.0, None) == -1
     assert L.p3m_drift_vjp(0, None, None, None, 1.0, 1.0, None) == 0    # empty: no-op
     assert L.p3m_drift_vjp(5, None, 2, None, 1.0, 1.0, None) == -1
