@@ -508,16 +508,26 @@ def test_back_to_back_calls_without_sync_match_separate_calls():
 
 # --------------------------------------------------------------- full-size workloads, sampled
 
-@pytest.mark.parametrize("name,precision,tol", [
-    ("zeldovich128", "fp32", 1e-3), ("zeldovich128", "fp64", 1e-6),
-    ("plummer256", "fp32", 1e-3), ("plummer256", "fp64", 1e-6)])
-def test_full_size_sampled_parity(name, precision, tol):
+@pytest.mark.parametrize("name,precision,tol,partials,cell_order", [
+    ("zeldovich128", "fp32", 1e-3, 0, False), ("zeldovich128", "fp64", 1e-6, 0, False),
+    ("plummer256", "fp32", 1e-3, 0, False), ("plummer256", "fp64", 1e-6, 0, False),
+    # the benchmark's force call: one-sided sum, force in cell order
+    ("plummer256", "fp32", 1e-3, 80, True), ("plummer256", "fp64", 1e-6, 80, False)])
+def test_full_size_sampled_parity(name, precision, tol, partials, cell_order):
     w = ics.workload(name)
     pos = workload_positions(name)
     tg, a_pp, a_pm = oracle_parts(name, n_targets=768, seed=3)
     ref = (a_pp + a_pm) * w.mass
-    with _plan_for(w, precision) as P:
-        F = host(P.force(dev(pos), w.mass))
+    with plan(w.grid_n, w.n, precision, rs_cells=w.rs_cells, cutoff_rs=w.cutoff_rs,
+              softening=w.softening, G=w.G, box=w.box, pair_partials=partials) as P:
+        if cell_order:
+            Fc, order = P.force_cell_order(dev(pos), w.mass)
+            order = order.cpu().numpy()
+            assert np.array_equal(np.sort(order), np.arange(w.n))
+            F = np.empty((3, w.n))
+            F[:, order] = host(Fc)
+        else:
+            F = host(P.force(dev(pos), w.mass))
     e = _err(F[:, tg], ref)
     print(name, precision, e)
     assert e["rms"] <= tol, e
