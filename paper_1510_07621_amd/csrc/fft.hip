@@ -3,8 +3,8 @@
 // Layout: the real grid is [x][y][z] (z fastest, ng^3 values); the spectrum
 // is [kx][ky][kz] with kz = 0..ng/2, each (kx, ky) row of ng/2 + 1 values
 // padded to spec_stride(ng) so that rows start on cache-line boundaries.
-// Five passes, each reading and writing the grid once, every transform done
-// in LDS:
+// Five passes, each reading and writing the grid once, each 1-D transform
+// held by one workgroup:
 //   1. z, real -> complex: each z-line of ng reals is transformed as ng/2
 //      complex values (even samples real, odd samples imaginary) and the
 //      ng/2 + 1 outputs are separated with the usual split step;
@@ -15,7 +15,9 @@
 // Transforms are radix-2: decimation in time (bit-reversed input, natural
 // output) forward and decimation in frequency (natural input, bit-reversed
 // output) inverse, so no pass needs a separate reordering step; three levels
-// at a time run in registers between LDS exchanges. All
+// at a time run in registers between LDS exchanges, the first level group of
+// a transform loading straight from global memory and the last storing
+// straight to it. All
 // transforms are unnormalised; the 1/ng^3 of the inverse is folded into the
 // Green's function
 //     G(k) = -4 pi G exp(-k^2 r_s^2) / (k^2 W(k)^p) / ng^3,  G(0) = 0,
