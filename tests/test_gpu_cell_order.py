@@ -132,3 +132,28 @@ def test_leapfrog_in_cell_order_follows_the_oracle(precision, partials):
     dx = np.minimum(dx, 1.0 - dx)
     assert np.max(dx) <= 1e-10 / grid
     assert np.max(np.abs(pg - po)) <= 1e-9 * np.max(np.abs(po))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65])
+def test_cell_order_small_and_ragged_sets(n):
+    """A handful of particles (one, two, a wave's worth minus and plus one):
+    the order is a permutation sorting the cells, the force at each slot is
+    p3m_force's for that particle, and the reordering kick of that force is
+    the oracle's kick, bit for bit."""
+    from paper_1510_07621_amd import binding
+    grid = 16
+    pos = ics.uniform(n, seed=40 + n)
+    m = 1.0 / max(n, 1)
+    x = dev(pos)
+    with plan(grid, max(n, 1), "fp64", pair_partials=80) as P:
+        F = host(P.force(x, m))
+        Fc, order = P.force_cell_order(x, m)
+        Fc, order = host(Fc), order.cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.all(np.diff(_cells(pos[:, order], grid)) >= 0)
+    assert np.allclose(Fc, F[:, order], rtol=1e-12, atol=1e-12 * np.abs(F).max())
+    p = np.random.default_rng(n).normal(size=(3, n))
+    po, mo, _, _ = binding.kick_reorder(torch.as_tensor(order, device="cuda"), x, dev(p),
+                                        dev(Fc), 0.25)
+    assert np.array_equal(host(mo), integrate.kick(p[:, order], Fc, 0.25))
+    assert np.array_equal(host(po), pos[:, order])
