@@ -465,8 +465,7 @@ k_fft_x_green(typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
 // divided by W(k)^2 when deconvolving, is added with its full-space
 // multiplicity (1 on the kz = 0 and Nyquist planes, else 2) into its shell
 // b = floor(|n| - 1/2): acc = [power sums | |n| sums | mode counts][nbins],
-// then the top-hat-weighted sum for sigma and rho_0 (the k = 0 value). The
-// modes are summed straight from the forward transform's top level group.
+// then the top-hat-weighted sum for sigma and rho_0 (the k = 0 value).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int kc,
@@ -529,9 +528,16 @@ k_fft_x_power(const typename Vec<T>::v2* __restrict__ spec, int ng, int lg, int 
     }
     atomicAdd(&hist[3 * nbins], mult * pw * wt * wt);
   };
-  // (the histogram's clearing is ordered before the sums by the transform's
-  // barriers)
-  col_transform<T, false>(buf, col, xs, kn, kc, lg, tw, twl, NoMid{}, shells);
+  // The transform's top level group stores the modes to LDS; the shell sums
+  // (double precision, kept out of the transform's registers) then read them,
+  // consecutive threads on consecutive columns. (The histogram's clearing is
+  // ordered before the sums by the transform's barriers.)
+  col_transform<T, false>(buf, col, xs, kn, kc, lg, tw, twl, NoMid{}, ColLds<T2>{buf, kc});
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ng * kc; idx += kThreads) {
+    const int kx = idx / kc, c = idx - kx * kc;
+    shells(kx, c, buf[pd(idx)]);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * nbins + 1; i += kThreads)
     if (hist[i] != 0.0) atomicAdd(&acc[i], hist[i]);
