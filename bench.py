@@ -43,13 +43,13 @@ HEADLINE_PARTIALS = 80      # one-sided pair sum between dense groups (clustered
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-PAIR_SOURCES = ("pair.hip", "react.hip")
+PAIR_SOURCES = ("pair.hip", "react.hip", "p3m_internal.h")
 
 
 def counter_record(name):
     """A committed counter summary of the pair stage (profiles/<name>.json),
-    or None when the pair kernel's or the gather's source changed after the
-    counters were taken."""
+    or None when the source of the pair kernel, of the gather or of the
+    constants they share changed after the counters were taken."""
     import hashlib
     try:
         with open(os.path.join(PROFILES, name + ".json")) as f:

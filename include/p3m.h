@@ -76,13 +76,13 @@ typedef struct p3m_params {
                              Ewald correction of pp_ewald_force                    */
   int32_t pair_partials;  /* short-range sum: 0 evaluates every pair from both
                              sides; > 0 evaluates a pair of particles in two
-                             dense groups (more than 128 particles each) once
+                             dense groups (more than 48 particles each) once
                              (the force on one is minus that on the other) and
                              keeps the reactions as partials, of which the plan
                              holds pair_partials per particle (80 suits strongly
                              clustered sets); a call that needs more falls back
                              to both sides. Pays on clustered sets (256^3
-                             Plummer mix: -7 %), not on smooth ones            */
+                             Plummer mix: -11 %), not on smooth ones            */
 } p3m_params;
 
 /* Opaque plan: derived geometry, device workspace, and optional stage timers. */

@@ -40,13 +40,15 @@ __host__ __device__ inline int spec_stride(int ng) { return ((ng >> 1) + 1 + 15)
 // displaced lattice, 64 on the 256^3 Plummer mix).
 constexpr int64_t kPartialsPerParticle = 80;
 // A group is dense (pairs with other dense groups evaluated once) above
-// this many particles: two chunks of items. (Above one chunk, 64, the
-// displaced lattice at one particle per cell made 40 % of its groups dense
-// and its second, small chunks wrote as many partials as the first: 2.63 ->
-// 3.18 ms for its short-range sum, while the clustered 256^3 set gained
-// only 38.9 -> 38.2 ms.)
+// this many particles. Measured on the clustered 256^3 set (FP32 pair
+// kernel + gather per force call): above 128 particles 35.3 + 3.9 ms, above
+// 64 34.0 + 4.7, above 48 33.4 + 5.1, above 32 32.9 + 5.8 ms: fewer
+// evaluations, more partials to gather. On a displaced lattice at one
+// particle per cell (64 per group) most groups are then dense and the
+// one-sided sum does not pay there (2.63 -> 3.18 ms above 64), which is
+// why it is a plan option for clustered input.
 #ifndef P3M_DENSE_MIN
-#define P3M_DENSE_MIN 128
+#define P3M_DENSE_MIN 48
 #endif
 constexpr int kDenseMin = P3M_DENSE_MIN;
 constexpr int64_t kPartialsSlack = 65536;
