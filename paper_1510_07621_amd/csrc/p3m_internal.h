@@ -94,7 +94,7 @@ struct Workspace {
   long long* gtot = nullptr;    // [ngroup]  reaction partials per i-group
   long long* gbase = nullptr;   // [ngroup+1] exclusive scan of gtot; [ngroup] = total
   long long* gscan_tmp = nullptr;  // tile sums of that scan
-  void* rpart = nullptr;        // [3][rcap] reaction partials (T), SoA
+  void* rpart = nullptr;        // [rcap][3] reaction partials (T), components together
   void* acc_mesh = nullptr;     // [n_max]   sorted mesh acceleration of a one-sided force (T4)
   // adjoint workspace (plans created with params.adjoint != 0)
   void* lam = nullptr;          // [n_max]   force cotangent in sorted order (T4)

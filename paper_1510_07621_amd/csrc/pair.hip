@@ -109,7 +109,7 @@ struct PairArgs {
   unsigned long long* __restrict__ counter;      // pair count mode
   // one-sided sum between dense groups: the stencil's group segments,
   // particles per group, per-group reaction offsets and partial bases, the
-  // partials [3][rcap] and their total this call (gbase[ngroup])
+  // partials [rcap][3] and their total this call (gbase[ngroup])
   const int4* __restrict__ segrows;
   int nseg, npos;
   const int32_t* __restrict__ gntot;
@@ -908,10 +908,10 @@ __device__ __forceinline__ void pair_item(const PairArgs<T>& A, SH& S, int gx0,
             if (rp >= 0) idx = ibase + rp + (c0 + q - S.d_pre[dd[e]]);
           }
           if (idx >= 0 && idx < ptotal) {    // (always below: a guard only)
-            const T4 r = S.jb[q];
-            px[idx] = r.x;
-            px[A.rcap + idx] = r.y;
-            px[2 * A.rcap + idx] = r.z;
+            const T4 r = S.jb[q];            // partial idx: 3 components together
+            px[3 * idx] = r.x;
+            px[3 * idx + 1] = r.y;
+            px[3 * idx + 2] = r.z;
           }
         }
       }

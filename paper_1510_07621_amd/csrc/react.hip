@@ -227,7 +227,7 @@ struct GatherArgs {
   const int32_t* __restrict__ gipre;
   const int32_t* __restrict__ gntot;
   const long long* __restrict__ gbase;           // [ngroup + 1]
-  const T* __restrict__ rpart;                   // [3][rcap]
+  const T* __restrict__ rpart;                   // [rcap][3]
   long long rcap;
   int npos, lg, G, lgG;
   int64_t ngroup;
@@ -271,9 +271,7 @@ k_react_gather(GatherArgs<T> A) {
   const int64_t gs = ((int64_t)gx << (2 * lgd)) | ((int64_t)gy << lgd) | gz;
   const int ntot_s = A.gntot[gs];
   if (total <= A.rcap && ntot_s > kDenseMin) {   // one-sided sum, dense group: reactions
-    const T* px = A.rpart;
-    const T* py = A.rpart + A.rcap;
-    const T* pz = A.rpart + 2 * A.rcap;
+    const T* pr = A.rpart;                   // partial idx at pr[3 idx .. 3 idx + 2]
     const long long last = total > 0 ? total - 1 : 0;
     const int colbase = ((cx << A.lg) | cy) << A.lg;
     const int np1 = A.npos + 1;
@@ -288,13 +286,13 @@ k_react_gather(GatherArgs<T> A) {
         const int L = A.rowoff[gs * np1 + A.npos];
         const long long gb = A.gbase[gs];
 #pragma unroll 4
-        for (int ch = 0; ch < (fi >> 6); ++ch) {
+        for (int ch = 0; ch < fi / kChunk; ++ch) {
           // (the clamp never acts: a guard that keeps the loads in flight together)
           const long long idx =
               min(item_base(gb, ntot_s, L, ch) + (fi - kChunk * (ch + 1)), last);
-          sx += px[idx];
-          sy += py[idx];
-          sz += pz[idx];
+          sx += pr[3 * idx];
+          sy += pr[3 * idx + 1];
+          sz += pr[3 * idx + 2];
         }
       }
     }
@@ -324,9 +322,9 @@ k_react_gather(GatherArgs<T> A) {
       for (int ch = 0; ch < K; ++ch) {
         const long long idx =
             min(item_base(gb, ntot, L, ch) + max(ntot - kChunk * (ch + 1), 0) + q, last);
-        sx += px[idx];
-        sy += py[idx];
-        sz += pz[idx];
+        sx += pr[3 * idx];
+        sy += pr[3 * idx + 1];
+        sz += pr[3 * idx + 2];
       }
     }
     const double f = UM ? A.rscale * (double)rs.w : A.rscale;
