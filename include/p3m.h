@@ -76,7 +76,7 @@ typedef struct p3m_params {
                              Ewald correction of pp_ewald_force                    */
   int32_t pair_partials;  /* short-range sum: 0 evaluates every pair from both
                              sides; > 0 evaluates a pair of particles in two
-                             dense groups (more than 48 particles each) once
+                             dense groups (more than 32 particles each) once
                              (the force on one is minus that on the other) and
                              keeps the reactions as partials, of which the plan
                              holds pair_partials per particle (80 suits strongly

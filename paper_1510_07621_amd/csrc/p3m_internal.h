@@ -40,14 +40,15 @@ __host__ __device__ inline int spec_stride(int ng) { return ((ng >> 1) + 1 + 15)
 constexpr int64_t kPartialsPerParticle = 80;
 // A group is dense (pairs with other dense groups evaluated once) above
 // this many particles. Measured on the clustered 256^3 set (FP32 pair
-// kernel + gather per force call): above 128 particles 35.3 + 3.9 ms, above
-// 64 34.0 + 4.7, above 48 33.4 + 5.1, above 32 32.9 + 5.8 ms: fewer
-// evaluations, more partials to gather. On a displaced lattice at one
-// particle per cell (64 per group) most groups are then dense and the
-// one-sided sum does not pay there (2.63 -> 3.18 ms above 64), which is
-// why it is a plan option for clustered input.
+// kernel + gather per force call, partials stored by record): above 48
+// particles 33.1 + 5.0 ms, above 40 32.8 + 5.2, above 32 32.5 + 5.6, above
+// 24 32.4 + 6.2 ms: fewer evaluations, more partials to gather; the sum is
+// flat from 48 down to 32, which has the faster pair kernel. On a displaced
+// lattice at one particle per cell (64 per group) most groups are then
+// dense and the one-sided sum does not pay there, which is why it is a plan
+// option for clustered input.
 #ifndef P3M_DENSE_MIN
-#define P3M_DENSE_MIN 48
+#define P3M_DENSE_MIN 32
 #endif
 constexpr int kDenseMin = P3M_DENSE_MIN;
 constexpr int64_t kPartialsSlack = 65536;
