@@ -36,7 +36,7 @@ constexpr int kMaxPowerBins = 512;     // shells of the power spectrum
 // passes straddled two cache lines.)
 __host__ __device__ inline int spec_stride(int ng) { return ((ng >> 1) + 1 + 15) & ~15; }
 // Reaction partials a plan holds for the one-sided pair sum by default, per
-// particle and in all (the 256^3 Plummer mix writes 50 per particle).
+// particle and in all (the 256^3 Plummer mix writes 56 per particle).
 constexpr int64_t kPartialsPerParticle = 80;
 // A group is dense (pairs with other dense groups evaluated once) above
 // this many particles. Measured on the clustered 256^3 set (FP32 pair
