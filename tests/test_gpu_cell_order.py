@@ -53,6 +53,13 @@ def test_force_in_cell_order_is_the_force_at_the_sorted_slots(precision, partial
     e = metrics.force_errors(Fc, F[:, order])
     tol = 1e-12 if precision == "fp64" else 1e-5
     assert e["rms"] < tol and e["max"] < 100 * tol, e
+    # FP32 force output through the same path
+    with plan(grid, n, precision, pair_partials=partials) as P:
+        F32, order32 = P.force_cell_order(x, m, fp32_out=True)
+        F32, order32 = host(F32).astype(np.float64), order32.cpu().numpy()
+    assert np.array_equal(np.sort(order32), np.arange(n))
+    e32 = metrics.force_errors(F32, F[:, order32])
+    assert e32["rms"] < max(tol, 1e-6), e32
 
 
 @pytest.mark.parametrize("with_arrays", [False, True])
