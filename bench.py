@@ -298,7 +298,7 @@ def powerspec_leg(binding, torch, name="zeldovich128", runs=20):
             "sigma_8cells": float(sig)}
 
 
-def adjoint_leg(binding, torch, name, precision, segment=None, keep_grad=False):
+def adjoint_leg(binding, torch, name, precision, segment=None, keep_grad=False, pair_partials=0):
     """Forward and backward time of the differentiable leapfrog: the
     workload's KDK steps from its positions at rest, loss = sum of squared
     final displacements (minimum image, from the initial positions), gradient
@@ -310,7 +310,7 @@ def adjoint_leg(binding, torch, name, precision, segment=None, keep_grad=False):
     x0 = torch.as_tensor(w.positions(), device="cuda").contiguous()
     p0 = torch.zeros_like(x0)
     seg = segment or max(1, math.ceil(math.sqrt(w.steps)))
-    P = plan_for(binding, w, precision, adjoint=True)
+    P = plan_for(binding, w, precision, pair_partials, adjoint=True)
 
     def run():
         x = x0.clone().requires_grad_(True)
@@ -334,6 +334,7 @@ def adjoint_leg(binding, torch, name, precision, segment=None, keep_grad=False):
         return g
     return {"workload": name, "n_particles": w.n, "grid_n": w.grid_n, "steps": w.steps,
             "dt": w.dt, "precision": precision, "checkpoint_segment": seg,
+            "pair_partials": pair_partials,
             "forward_s": tf, "backward_s": tb, "ratio": tb / tf, "loss": loss,
             "grad_rms": float(torch.sqrt((g * g).sum(0).mean()))}
 
