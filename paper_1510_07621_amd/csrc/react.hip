@@ -4,8 +4,9 @@
 // erfc-split pair law depends on the separation only, and it is odd in it),
 // and so is the pair term of the force adjoint. Where particles are dense,
 // the pair sum evaluates each such pair once and keeps the other particle's
-// share as a partial. A group is dense when it holds more than one chunk
-// (kChunk particles); a work item (group g, chunk a) of a dense group stages
+// share as a partial. A group is dense when it holds more than kDenseMin
+// particles; a work item (group g, chunk a of kChunk particles) of a dense
+// group stages
 //   1. its own group's particles from its chunk on (flattened index >= 64 a):
 //      its own chunk first (both sides of each pair evaluated, the item's own
 //      action only), then the later chunks, with their reactions;
@@ -15,8 +16,8 @@
 //      side), and none in a dense group at a negative offset (that group
 //      evaluates the pair);
 // and for every staged entry that takes a reaction it writes the reaction
-// the item's particles exert on that entry as one partial (3 components) at
-// a fixed place. Sparse groups evaluate every pair from both sides. This
+// the item's particles exert on that entry as one partial (its 3 components
+// together) at a fixed place. Sparse groups evaluate every pair from both sides. This
 // file holds the steps around the pair kernel:
 //   - per group: its particle count and the particles before each of its
 //     z-runs; per dense group the reaction entries before each positive
